@@ -1,0 +1,207 @@
+/*
+ * swmi — exact Smith-Waterman protein database search on AMD MI355X (gfx950).
+ *
+ * C ABI of the shared library libswmi.so.  Every entry point returns 0 on
+ * success or a negative SW_E* code; sw_last_error() then returns a message
+ * (thread-local, valid until the next call on the same thread).  No C++
+ * exception crosses this boundary.
+ *
+ * The method (section II.A, Eq. 1): for a query Q (length m) and a database
+ * sequence S (length n) the score is max over i, j of H(i,j) with
+ *   H(i,j) = max{0, H(i-1,j-1) + M[Q[j]][S[i]], E(i,j), F(i,j)}
+ *   E(i,j) = max{E(i-1,j) - alpha, H(i-1,j) - beta}
+ *   F(i,j) = max{F(i,j-1) - alpha, H(i,j-1) - beta}
+ * and H, E, F zero on row 0 and column 0.  alpha is the gap extension
+ * penalty, beta = gap open + extension.  The matrix row is the query residue
+ * (as in the query profile of section III.B.2).  Scores are exact int32.
+ *
+ * Memory: every pointer argument is HOST memory unless its name ends in
+ * _dev.  The library copies what it needs; callers keep ownership of their
+ * buffers and may free them as soon as a call returns.  The only objects the
+ * library allocates for the caller are the opaque sw_db / sw_server handles,
+ * released by sw_db_close / sw_server_stop.
+ *
+ * Threads: calls on one sw_db are serialised by an internal lock.  The server
+ * (sw_server_*) is the concurrent path; its submit/wait may be called from any
+ * number of threads.
+ */
+#ifndef SWMI_H
+#define SWMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_OK        0
+#define SW_EINVAL   (-1)   /* bad argument: code >= alphabet, alphabet not in 1..32,
+                              alpha < 0, beta < alpha, beta > 2^30, qlen < 1 or > 2^24,
+                              subject longer than 2^24, k < 1 or k > SW_MAX_K, NULL pointer */
+#define SW_ENOMEM   (-2)   /* host or device allocation failed */
+#define SW_EDEVICE  (-3)   /* a HIP runtime call or kernel launch failed */
+#define SW_EBUSY    (-4)   /* server: request queue full (back-pressure) */
+#define SW_ENOTFOUND (-5)  /* server: unknown or already collected ticket */
+#define SW_ESTOPPED (-6)   /* server: stopped before the request completed */
+
+#define SW_MAX_ALPHABET 32
+#define SW_MAX_LEN      (1 << 24)
+#define SW_MAX_K        4096
+
+typedef struct sw_db sw_db;
+typedef struct sw_server sw_server;
+
+/* Scoring scheme (section II.A).  matrix: alphabet*alphabet int8, row-major,
+ * matrix[q*alphabet + s] scores query residue q against subject residue s.
+ * 0 <= alpha <= beta <= 2^30.  alphabet must equal the database's. */
+typedef struct sw_scoring {
+    int32_t alphabet;
+    const int8_t *matrix;
+    int32_t alpha;
+    int32_t beta;
+} sw_scoring;
+
+/* Options for sw_db_open; pass NULL for defaults (all fields 0). */
+typedef struct sw_db_opts {
+    int32_t device;          /* HIP device ordinal; <= 0 means device 0 */
+    int32_t long_threshold;  /* subjects longer than this use the wave-per-pair kernel;
+                                0 = chosen from the length distribution, -1 = none
+                                (all subjects use the lane-per-subject kernel), 1 = all
+                                subjects use the wave-per-pair kernel */
+    int32_t reserved[6];
+} sw_db_opts;
+
+/* Lane tiers of the lane-per-subject kernel. */
+#define SW_TIER_AUTO  0
+#define SW_TIER_F16X2 1   /* two subjects per 32-bit lane, packed fp16 holding exact
+                             integers; exact while the best score < 1920, else the pair
+                             is flagged and recomputed in int32 */
+#define SW_TIER_I16X2 2   /* two subjects per lane, saturating int16; exact below 32767 */
+
+/* Search tuning knobs (planner overrides; 0 = let the planner/autotuner choose). */
+typedef struct sw_search_opts {
+    int32_t tier;           /* SW_TIER_* */
+    int32_t strip;          /* query columns per register strip: 16, 32 or 64 */
+    int32_t waves;          /* waves per workgroup of the lane-per-subject kernel: 4, 6, 8 */
+    int32_t sat_threshold;  /* test knob: if > 0, a narrow-tier lane whose best score reaches
+                               min(this, tier ceiling) is flagged and recomputed in int32 */
+    int32_t reserved[4];
+} sw_search_opts;
+
+/* Statistics of the last search call on a database handle. */
+typedef struct sw_stats {
+    int64_t cells;            /* sum over queries of |Q| * sum |S| (real residues) */
+    int64_t padded_cells;     /* cells actually evaluated, padding included */
+    int64_t inter_cells;      /* real cells handled by the lane-per-subject kernel */
+    int64_t recomputed_pairs; /* pairs flagged by a narrow tier and recomputed in int32 */
+    int64_t intra_pairs;      /* pairs evaluated by the wave-per-pair kernel */
+    double  kernel_ms;        /* device time of the alignment kernels (HIP events) */
+    double  total_ms;         /* wall time of the whole call */
+    double  inter_ms;         /* device time of the lane-per-subject kernel alone */
+    int32_t tier;             /* tier used */
+    int32_t strip;            /* strip width used */
+    int32_t waves;            /* waves per workgroup used */
+    int32_t reserved;
+} sw_stats;
+
+/* Open a database (section III, stage ii: sequences are sorted by length and
+ * laid out for the device once).
+ *   residues: concatenated codes, each < alphabet (offsets[n_seqs] bytes)
+ *   offsets:  n_seqs + 1 non-decreasing int64, offsets[0] == 0
+ *   n_seqs >= 0; zero-length sequences are allowed (score 0)
+ * Copies everything to device memory; *out receives the handle. */
+int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs,
+               int32_t alphabet, const sw_db_opts *opts, sw_db **out);
+
+/* Release a database and its device memory.  NULL is ignored. */
+void sw_db_close(sw_db *db);
+
+/* Number of sequences in the database (-1 for NULL). */
+int64_t sw_db_size(const sw_db *db);
+
+/* Override planner choices for later searches on this handle (NULL resets). */
+int sw_db_set_opts(sw_db *db, const sw_search_opts *opts);
+
+/* Statistics of the last search on this handle. */
+int sw_db_last_stats(sw_db *db, sw_stats *out);
+
+/* Score one query against every database sequence (section II.A, Eq. 1).
+ *   scores: n_seqs int32, in the caller's original database order
+ *   hip_stream: a hipStream_t to order the work on, or NULL for the library's own
+ * Returns after the scores are in host memory. */
+int sw_db_search(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
+                 int32_t *scores, void *hip_stream);
+
+/* Same, but scores_dev is DEVICE memory (n_seqs int32) on the database's device;
+ * returns once the work is enqueued on hip_stream (NULL = library stream,
+ * which is then synchronised before returning). */
+int sw_db_search_dev(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
+                     int32_t *scores_dev, void *hip_stream);
+
+/* The k best database sequences for one query (section III, stage iv: scores
+ * sorted in descending order; equal scores by ascending database index).
+ * top_scores[k], top_idx[k]; if k > n_seqs the tail is filled with -1. */
+int sw_db_topk(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
+               int32_t k, int32_t *top_scores, int64_t *top_idx, void *hip_stream);
+
+/* Many queries in one fused launch over the database.
+ *   q_res / q_off: nq queries concatenated, q_off has nq + 1 entries
+ *   top_scores / top_idx: nq * k (row per query), same order rules as sw_db_topk
+ *   all_scores: NULL, or nq * n_seqs int32 (row per query, database order) */
+int sw_db_search_batch(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off,
+                       const sw_scoring *sc, int32_t k, int32_t *top_scores, int64_t *top_idx,
+                       int32_t *all_scores, void *hip_stream);
+
+/* Run the autotuner: time the candidate plans on a sample of this database for
+ * the given query lengths and keep the fastest per query-length bucket.  If
+ * cache_path is non-NULL the table is read from / written to that JSON file. */
+int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,
+                   const char *cache_path);
+
+/* ---- serving (continuous batching over a resident database) ---- */
+
+typedef struct sw_server_opts {
+    int64_t memory_budget;   /* bytes of device memory for admitted requests' profiles and
+                                per-request state; 0 = 1 GiB */
+    int32_t max_active;      /* requests coalesced into one database pass; 0 = 64 */
+    int32_t queue_capacity;  /* waiting requests before submit returns SW_EBUSY; 0 = 65536 */
+    int32_t chunk_groups;    /* database chunk per launch, in groups of 128 subjects;
+                                0 = chosen by the server */
+    int32_t reserved[5];
+} sw_server_opts;
+
+typedef struct sw_req_stats {
+    double queue_ms;   /* submit -> admitted into the database scan */
+    double total_ms;   /* submit -> result ready */
+    int64_t cells;     /* |Q| * sum |S| */
+    int32_t passes;    /* database chunks this request rode on */
+    int32_t reserved;
+} sw_req_stats;
+
+/* Start a server over an open database.  The database must outlive the server
+ * and must not be searched directly while the server runs. */
+int sw_server_start(sw_db *db, const sw_server_opts *opts, sw_server **out);
+
+/* Queue one query (copied).  *ticket identifies it for sw_server_wait. */
+int sw_server_submit(sw_server *srv, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
+                     int32_t k, uint64_t *ticket);
+
+/* Block until the request completes; writes k scores / indices as sw_db_topk.
+ * stats may be NULL.  A ticket can be collected once. */
+int sw_server_wait(sw_server *srv, uint64_t ticket, int32_t *top_scores, int64_t *top_idx,
+                   sw_req_stats *stats);
+
+/* Stop the server: pending requests fail with SW_ESTOPPED.  NULL is ignored. */
+void sw_server_stop(sw_server *srv);
+
+/* Message for the last failed call on this thread ("" if none). */
+const char *sw_last_error(void);
+
+/* Library version string. */
+const char *sw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWMI_H */

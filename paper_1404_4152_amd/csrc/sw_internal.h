@@ -1,0 +1,98 @@
+// Internal interface between the host library (sw_host.cpp) and the gfx950
+// kernels (sw_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace swmi {
+
+// Residue code reserved for padding: it scores 0 against every query residue
+// (the dummy residue of section III.B.1).  Real codes are 0..alphabet-1, so
+// the pad code is `alphabet` and profiles have R = alphabet + 1 rows.
+// Lanes per wave on gfx950.
+constexpr int kWave = 64;
+// Subjects per lane-per-subject group: 64 lanes x 2 packed halves.
+constexpr int kGroup = 2 * kWave;
+// Rows per residue/boundary chunk of the lane-per-subject kernel.
+constexpr int kChunk = 4;
+// Query profiles are padded to a multiple of this many columns.
+constexpr int kQPad = 64;
+
+// Exactness ceilings of the narrow tiers (see sw_kernels.hip for the proofs).
+constexpr int kThrF16 = 1920;    // fp16 holds every integer in [-2048, 2048]
+constexpr int kThrI16 = 32767;   // saturating int16
+
+enum Tier : int { TIER_F16X2 = 1, TIER_I16X2 = 2 };
+
+// Per-call description of the queries on the device.
+struct QuerySet {
+    const int8_t *qp;        // profiles: query q at qp + qp_off[q], R rows x mpad[q] cols
+    const int64_t *qp_off;
+    const int32_t *mpad;     // padded length (multiple of kQPad)
+    const int32_t *qlen;     // real length
+};
+
+struct InterArgs {
+    const uint16_t *codes;   // pair codes lo*R + hi per (chunk, lane, row)
+    const int64_t *grp_base; // first code (uint16 index) of each group
+    const int32_t *grp_rows; // rows of each group (multiple of kChunk)
+    const int32_t *grp_ids;  // caller ids: [g*128 + lane] lo half, [g*128 + 64 + lane] hi half
+    int32_t n_groups;
+    const int32_t *item_q;   // work item -> query
+    const int32_t *item_g;   // work item -> first group of its block of `waves` groups
+    int32_t n_items;
+    int32_t *counter;        // work-queue head, zero before launch
+    QuerySet qs;
+    int32_t R;
+    int32_t alpha, beta;     // already clamped for the tier
+    int32_t thr;             // a lane whose best reaches thr is flagged
+    uint32_t *scratch;       // boundary columns: per (slot, wave) max_rows * 64 * 2 dwords
+    int32_t max_rows;
+    int32_t *scores;         // [query][n_seqs], caller order
+    int64_t n_seqs;
+    int32_t *ovf_q, *ovf_id, *ovf_count;
+    int64_t ovf_cap;
+};
+
+struct IntraArgs {
+    const uint8_t *res;      // all residues, caller order
+    const int64_t *off;      // n_seqs + 1 offsets
+    const int32_t *item_q;   // work item -> query
+    const int32_t *item_ids; // work item -> `waves` subject ids (-1 = none)
+    int32_t n_items;         // used when n_items_dev == nullptr
+    const int32_t *n_items_dev;
+    int32_t *counter;
+    QuerySet qs;
+    int32_t R;
+    int32_t alpha, beta;
+    int32_t *pass_scratch;   // per (slot, wave): (max_len_pad) x 2 int32
+    int64_t max_len_pad;     // rows per scratch slot (>= longest subject rounded to 64, + 128)
+    int32_t *scores;
+    int64_t n_seqs;
+};
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
+                        hipStream_t st);
+int inter_lds_bytes(int R, int strip);
+int inter_max_grid(int R, int strip, int waves);      // resident workgroups that fit
+
+hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
+int intra_lds_bytes(int R, int T);
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
+
+// Top-k by (score desc, index asc) over rows of `n` scores, `nq` rows.
+struct TopkWork {
+    uint32_t *hist;      // nq * 256
+    int32_t *state;      // nq * 4: prefix, kleft, cnt_gt, pad
+    int32_t *eqcnt;      // nq * kTopkBlocks
+    int32_t *cand_s;     // nq * k
+    int32_t *cand_i;     // nq * k
+};
+constexpr int kTopkBlocks = 256;
+hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, int32_t k,
+                       const TopkWork &w, int32_t *top_s, int64_t *top_i, hipStream_t st);
+
+}  // namespace swmi

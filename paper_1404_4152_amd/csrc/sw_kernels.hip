@@ -1,0 +1,740 @@
+// gfx950 kernels for exact affine-gap Smith-Waterman database search.
+//
+// Recurrence (section II.A, Eq. 1), with i over the subject and j over the
+// query, and substitution score M[Q[j]][S[i]]:
+//   H(i,j) = max{0, H(i-1,j-1) + M, E(i,j), F(i,j)}
+//   E(i,j) = max{E(i-1,j) - alpha, H(i-1,j) - beta}
+//   F(i,j) = max{F(i,j-1) - alpha, H(i,j-1) - beta}
+// Every kernel evaluates it in the same per-cell form:
+//   h = max(hdiag + s, e, f); t = h - beta; e' = max(e - alpha, t, 0);
+//   f' = max(f - alpha, t, 0); best = max(best, h)
+// Flooring E and F at 0 leaves H unchanged: H = max(0, ...) already, and by
+// induction the floored E is max(E, 0) because alpha >= 0.  Sharing
+// t = h - beta between E (next row) and F (next column) gives 7.5 VALU ops per
+// cell with a 3-input max, the running best taking one max3 per two cells.
+//
+// Two kernels:
+//  * inter_kernel: one lane per subject, two subjects per 32-bit lane in packed
+//    16-bit halves (the inter-sequence model of section III.B).  Subjects are
+//    length-sorted into groups of 128; a group is one wavefront.  Each lane
+//    keeps a strip of T query columns of H and E in registers and streams its
+//    subjects' rows; the column crossing to the next strip (H and F of every
+//    row) goes through a per-wave boundary buffer.  This is the tiled SW
+//    computation of the conclusion.  The substitution scores of the strip sit
+//    in LDS as a pair profile P[a*R + b][j] = (M[q_j][a], M[q_j][b]) so that one
+//    dword read feeds both halves of a lane.
+//  * intra_kernel: one wavefront per (query, subject) pair, int32 and exact
+//    (the intra-sequence model of section III.C, laid out as a systolic
+//    array along anti-diagonals rather than striped).  Lane l owns T query
+//    columns; at step t it computes subject row t - l; H and F of its last
+//    column move to lane l+1 with a DPP wave shift.  Serves long subjects,
+//    small databases and the exact recompute of flagged narrow-tier lanes.
+//
+// Narrow-tier exactness.  A tier computes exactly while every intermediate
+// value is representable; it flags a lane whose best reaches the tier's
+// threshold `thr` and the host recomputes that pair in int32.  Claim: if the
+// true best is < thr, the tier's result equals it; otherwise the lane is
+// flagged.  All values up to the first cell whose true H reaches thr are
+// exact (nonnegative values stay below thr + 127, negative values only lose
+// magnitude, and floors at 0 hide them), so that cell's computed H is its true
+// value >= thr and the running best reaches thr.
+//   F16X2: fp16 holds every integer in [-2048, 2048]; thr = 1920 keeps
+//          thr - 1 + max(M) <= 2048 for |M| <= 127.  alpha and beta are
+//          clamped to 2048: for lanes below thr a larger penalty gives the same
+//          (zero-floored) E and F.  Once flagged, values may round or reach
+//          +inf but never NaN (only finite constants are subtracted).
+//   I16X2: saturating int16; thr = 32767, the saturation ceiling.
+#include "sw_internal.h"
+
+namespace swmi {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef short s2 __attribute__((ext_vector_type(2)));
+typedef unsigned short u2 __attribute__((ext_vector_type(2)));
+
+template <class V>
+__device__ __forceinline__ V as_v(uint32_t x) { return __builtin_bit_cast(V, x); }
+template <class V>
+__device__ __forceinline__ uint32_t as_u(V v) { return __builtin_bit_cast(uint32_t, v); }
+
+// ---------------------------------------------------------------------------
+// Lane arithmetic of the two packed tiers.
+// ---------------------------------------------------------------------------
+template <int TIER> struct Lane;
+
+template <> struct Lane<TIER_F16X2> {
+    typedef h2 V;
+    V nalpha, nbeta;
+    __device__ Lane(int alpha, int beta) {
+        const _Float16 a = (_Float16)(float)(-alpha), b = (_Float16)(float)(-beta);
+        nalpha = V{a, a};
+        nbeta = V{b, b};
+    }
+    static __device__ __forceinline__ V zero() { return V{(_Float16)0.0f, (_Float16)0.0f}; }
+    static __device__ __forceinline__ V max3(V a, V b, V c) {
+        return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
+    }
+    static __device__ __forceinline__ uint16_t enc(int v) {
+        return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
+    }
+    __device__ __forceinline__ V diag(V hd, V s) const { return hd + s; }
+    __device__ __forceinline__ V hmax(V hd, V e, V f) const { return max3(hd, e, f); }
+    __device__ __forceinline__ V open(V h) const { return h + nbeta; }
+    __device__ __forceinline__ V gap(V g, V t) const { return max3(g + nalpha, t, zero()); }
+    __device__ __forceinline__ V best2(V b, V h0, V h1) const { return max3(b, h0, h1); }
+    // (score, flagged) of one half
+    static __device__ __forceinline__ int value(V b, int half, int thr, bool *flag) {
+        const float x = half ? (float)b.y : (float)b.x;
+        *flag = !(x < (float)thr);
+        return *flag ? -1 : (int)x;
+    }
+};
+
+template <> struct Lane<TIER_I16X2> {
+    typedef s2 V;
+    u2 ua, ub;
+    __device__ Lane(int alpha, int beta) {
+        ua = u2{(unsigned short)alpha, (unsigned short)alpha};
+        ub = u2{(unsigned short)beta, (unsigned short)beta};
+    }
+    static __device__ __forceinline__ V zero() { return V{0, 0}; }
+    static __device__ __forceinline__ uint16_t enc(int v) { return (uint16_t)(int16_t)v; }
+    __device__ __forceinline__ V diag(V hd, V s) const { return __builtin_elementwise_add_sat(hd, s); }
+    __device__ __forceinline__ V hmax(V hd, V e, V f) const {
+        return __builtin_elementwise_max(__builtin_elementwise_max(hd, e), f);
+    }
+    // h >= 0 here, so the unsigned saturating subtraction is max(h - beta, 0).
+    __device__ __forceinline__ V open(V h) const {
+        return (V)__builtin_elementwise_sub_sat((u2)h, ub);
+    }
+    __device__ __forceinline__ V gap(V g, V t) const {
+        return __builtin_elementwise_max((V)__builtin_elementwise_sub_sat((u2)g, ua), t);
+    }
+    __device__ __forceinline__ V best2(V b, V h0, V h1) const {
+        return __builtin_elementwise_max(__builtin_elementwise_max(b, h0), h1);
+    }
+    static __device__ __forceinline__ int value(V b, int half, int thr, bool *flag) {
+        const int x = half ? (int)b.y : (int)b.x;
+        *flag = x >= thr;
+        return *flag ? -1 : x;
+    }
+};
+
+// a / R for a < R*R <= 1089 via a multiply (checked on the host for every R).
+__device__ __forceinline__ int div_r(int a, int magic) { return (a * magic) >> 16; }
+
+// ---------------------------------------------------------------------------
+// Lane-per-subject kernel.
+// ---------------------------------------------------------------------------
+template <int T, int TIER>
+struct Strip {
+    typedef Lane<TIER> L;
+    typedef typename L::V V;
+
+    // One subject row across the strip.  P: the row's pair-profile values.
+    // hb_prev = H(i-1, j0-1), fin = F(i, j0).  Returns H(i, j0+T-1), F(i, j0+T).
+    static __device__ __forceinline__ void row(const L &ops, V (&H)[T], V (&E)[T],
+                                               const uint4 (&P)[T / 4], uint32_t hb_prev,
+                                               uint32_t fin, V &best, uint32_t &hout,
+                                               uint32_t &fout) {
+        V hdiag = as_v<V>(hb_prev);
+        V f = as_v<V>(fin);
+#pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) {
+            const uint32_t pv[4] = {P[j4].x, P[j4].y, P[j4].z, P[j4].w};
+#pragma unroll
+            for (int u = 0; u < 4; u += 2) {
+                const int j = j4 * 4 + u;
+                V h0, h1;
+                {
+                    const V hold = H[j];
+                    h0 = ops.hmax(ops.diag(hdiag, as_v<V>(pv[u])), E[j], f);
+                    const V t = ops.open(h0);
+                    E[j] = ops.gap(E[j], t);
+                    f = ops.gap(f, t);
+                    H[j] = h0;
+                    hdiag = hold;
+                }
+                {
+                    const V hold = H[j + 1];
+                    h1 = ops.hmax(ops.diag(hdiag, as_v<V>(pv[u + 1])), E[j + 1], f);
+                    const V t = ops.open(h1);
+                    E[j + 1] = ops.gap(E[j + 1], t);
+                    f = ops.gap(f, t);
+                    H[j + 1] = h1;
+                    hdiag = hold;
+                }
+                best = ops.best2(best, h0, h1);
+            }
+        }
+        hout = as_u(H[T - 1]);
+        fout = as_u(f);
+        // Materialise this row's state here: without the fences the compiler
+        // sinks E and the running best into the next rows and keeps several
+        // rows of H alive, which spills.
+#pragma unroll
+        for (int j = 0; j < T; ++j) asm volatile("" : "+v"(H[j]), "+v"(E[j]));
+        asm volatile("" : "+v"(best));
+    }
+
+    static __device__ __forceinline__ void load(uint4 (&P)[T / 4], const uint32_t *lds, int RS,
+                                                uint32_t code) {
+        const uint4 *src = (const uint4 *)(lds + code * RS);
+#pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+    }
+};
+
+// Occupancy the register budget is sized for (waves per SIMD).
+template <int T> struct InterOcc { static constexpr int value = T <= 16 ? 3 : (T <= 32 ? 2 : 1); };
+
+template <int T, int W, int TIER>
+__global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(InterArgs a, int magic) {
+    typedef Lane<TIER> L;
+    typedef typename L::V V;
+    constexpr int RS = T + 4;                 // dwords per pair-profile row (padded)
+    extern __shared__ uint32_t lds[];
+    const int R = a.R;
+    const int RR = R * R;
+    uint32_t *stage = lds + RR * RS;          // R x T/2 dwords: the strip's profile, 16-bit
+    __shared__ int s_item;
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const L ops(a.alpha, a.beta);
+    uint32_t *wsc = a.scratch + ((size_t)(blockIdx.x * W + w) * (size_t)a.max_rows) * 128 + lane * 8;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= a.n_items) break;
+        const int q = a.item_q[it];
+        const int g = a.item_g[it] + w;
+        const bool active = g < a.n_groups;
+        const int rows = active ? a.grp_rows[g] : 0;
+        const int mp = a.qs.mpad[q];
+        const int nstrips = mp / T;
+        const int8_t *qp = a.qs.qp + a.qs.qp_off[q];
+        const uint16_t *codes = a.codes + (active ? a.grp_base[g] : 0) + lane * 4;
+        V best = L::zero();
+
+        for (int k = 0; k < nstrips; ++k) {
+            __syncthreads();   // previous table no longer read; s_item consumed
+            for (int e = threadIdx.x; e < R * (T / 2); e += W * 64) {
+                const int r = e / (T / 2), jj = e - r * (T / 2);
+                const int8_t *src = qp + (size_t)r * mp + k * T + 2 * jj;
+                stage[e] = (uint32_t)L::enc(src[0]) | ((uint32_t)L::enc(src[1]) << 16);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < RR * (T / 2); e += W * 64) {
+                const int row = e / (T / 2), jj = e - row * (T / 2);
+                const int ra = div_r(row, magic), rb = row - ra * R;
+                const uint32_t pa = stage[ra * (T / 2) + jj], pb = stage[rb * (T / 2) + jj];
+                uint2 v;
+                v.x = (pa & 0xffffu) | (pb << 16);
+                v.y = (pa >> 16) | (pb & 0xffff0000u);
+                *(uint2 *)(lds + row * RS + 2 * jj) = v;
+            }
+            __syncthreads();
+            if (!active) continue;
+
+            V H[T], E[T];
+#pragma unroll
+            for (int j = 0; j < T; ++j) { H[j] = L::zero(); E[j] = L::zero(); }
+            uint32_t hb_prev = 0;
+            const bool has_in = k > 0, has_out = k + 1 < nstrips;
+            const int nch = rows / kChunk;
+            // Pair codes are fetched two chunks ahead, boundary columns one chunk
+            // ahead, and the profile row of the next subject row while the
+            // current one computes.
+            uint2 cd = *(const uint2 *)codes;
+            uint2 cd_n = nch > 1 ? *(const uint2 *)(codes + 256) : cd;
+            uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+            if (has_in) {
+                b0 = ((const uint4 *)wsc)[0];
+                b1 = ((const uint4 *)wsc)[1];
+            }
+            uint4 P0[T / 4], P1[T / 4];
+            Strip<T, TIER>::load(P0, lds, RS, cd.x & 0xffffu);
+            for (int c = 0; c < nch; ++c) {
+                const uint2 cd_nn = c + 2 < nch ? *(const uint2 *)(codes + (size_t)(c + 2) * 256) : cd_n;
+                uint4 b0n = make_uint4(0, 0, 0, 0), b1n = make_uint4(0, 0, 0, 0);
+                if (has_in && c + 1 < nch) {
+                    b0n = ((const uint4 *)(wsc + (size_t)(c + 1) * 512))[0];
+                    b1n = ((const uint4 *)(wsc + (size_t)(c + 1) * 512))[1];
+                }
+                uint32_t out[8];
+                Strip<T, TIER>::load(P1, lds, RS, cd.x >> 16);
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::row(ops, H, E, P0, hb_prev, b0.y, best, out[0], out[1]);
+                hb_prev = b0.x;
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::load(P0, lds, RS, cd.y & 0xffffu);
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::row(ops, H, E, P1, hb_prev, b0.w, best, out[2], out[3]);
+                hb_prev = b0.z;
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::load(P1, lds, RS, cd.y >> 16);
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::row(ops, H, E, P0, hb_prev, b1.y, best, out[4], out[5]);
+                hb_prev = b1.x;
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::load(P0, lds, RS, cd_n.x & 0xffffu);
+                __builtin_amdgcn_sched_barrier(0);
+                Strip<T, TIER>::row(ops, H, E, P1, hb_prev, b1.w, best, out[6], out[7]);
+                hb_prev = b1.z;
+                __builtin_amdgcn_sched_barrier(0);
+                if (has_out) {
+                    uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
+                    dst[0] = make_uint4(out[0], out[1], out[2], out[3]);
+                    dst[1] = make_uint4(out[4], out[5], out[6], out[7]);
+                }
+                cd = cd_n;
+                cd_n = cd_nn;
+                b0 = b0n;
+                b1 = b1n;
+            }
+        }
+        if (active) {
+            const int ids[2] = {a.grp_ids[g * kGroup + lane], a.grp_ids[g * kGroup + kWave + lane]};
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int id = ids[half];
+                if (id < 0) continue;
+                bool flag;
+                const int v = L::value(best, half, a.thr, &flag);
+                a.scores[(size_t)q * a.n_seqs + id] = v;
+                if (flag) {
+                    const int pos = atomicAdd(a.ovf_count, 1);
+                    if (pos < a.ovf_cap) {
+                        a.ovf_q[pos] = q;
+                        a.ovf_id[pos] = id;
+                    }
+                }
+            }
+        }
+    }
+}
+
+int inter_lds_bytes(int R, int strip) {
+    return (R * R * (strip + 4) + R * (strip / 2)) * 4;
+}
+
+static int lds_per_cu() { return 160 * 1024; }
+
+int inter_max_grid(int R, int strip, int waves) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip) + 64);
+    const int by_waves = 32 / waves;   // conservative: 8 waves per SIMD at most
+    int per_cu = by_lds < by_waves ? by_lds : by_waves;
+    if (per_cu < 1) per_cu = 1;
+    return per_cu * cus;
+}
+
+template <int T, int W, int TIER>
+static hipError_t launch_inter_t(const InterArgs &a, int grid, hipStream_t st) {
+    int magic = (65536 + a.R - 1) / a.R;
+    const int lds = inter_lds_bytes(a.R, T);
+    hipError_t e = hipFuncSetAttribute((const void *)inter_kernel<T, W, TIER>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((inter_kernel<T, W, TIER>), dim3(grid), dim3(W * 64), lds, st, a, magic);
+    return hipGetLastError();
+}
+
+template <int TIER>
+static hipError_t launch_inter_tier(const InterArgs &a, int strip, int waves, int grid,
+                                    hipStream_t st) {
+#define SWMI_INTER_CASE(T_, W_) \
+    if (strip == T_ && waves == W_) return launch_inter_t<T_, W_, TIER>(a, grid, st);
+    SWMI_INTER_CASE(16, 4) SWMI_INTER_CASE(16, 8)
+    SWMI_INTER_CASE(32, 4) SWMI_INTER_CASE(32, 6) SWMI_INTER_CASE(32, 8)
+    SWMI_INTER_CASE(64, 4)
+#undef SWMI_INTER_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
+                        hipStream_t st) {
+    if (tier == TIER_F16X2) return launch_inter_tier<TIER_F16X2>(a, strip, waves, grid, st);
+    if (tier == TIER_I16X2) return launch_inter_tier<TIER_I16X2>(a, strip, waves, grid, st);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Wave-per-pair kernel (int32, exact).
+// ---------------------------------------------------------------------------
+// DPP wave shifts: lane i takes lane i-1 (shr) or i+1 (shl); the lane with no
+// source keeps `old`.
+__device__ __forceinline__ int shr1(int old, int src) {
+    return __builtin_amdgcn_update_dpp(old, src, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int shl1(int old, int src) {
+    return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);
+}
+
+template <int T>
+__device__ __forceinline__ void intra_row(int (&H)[T], int (&E)[T], const uint2 *pr, int hb_prev,
+                                          int fin, int alpha, int beta, int &best, int &hout,
+                                          int &fout) {
+    int hdiag = hb_prev, f = fin;
+#pragma unroll
+    for (int j4 = 0; j4 < T / 4; ++j4) {
+        const uint2 p = pr[j4];
+        const uint32_t pv[2] = {p.x, p.y};
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+            const int j = j4 * 4 + u;
+            const uint32_t wd = pv[u >> 1];
+            int h0, h1;
+            {
+                const int hold = H[j];
+                h0 = __builtin_elementwise_max(
+                    __builtin_elementwise_max(hdiag + (int)(short)(wd & 0xffffu), E[j]), f);
+                const int t = h0 - beta;
+                E[j] = __builtin_elementwise_max(__builtin_elementwise_max(E[j] - alpha, t), 0);
+                f = __builtin_elementwise_max(__builtin_elementwise_max(f - alpha, t), 0);
+                H[j] = h0;
+                hdiag = hold;
+            }
+            {
+                const int hold = H[j + 1];
+                h1 = __builtin_elementwise_max(
+                    __builtin_elementwise_max(hdiag + (int)(short)(wd >> 16), E[j + 1]), f);
+                const int t = h1 - beta;
+                E[j + 1] = __builtin_elementwise_max(__builtin_elementwise_max(E[j + 1] - alpha, t), 0);
+                f = __builtin_elementwise_max(__builtin_elementwise_max(f - alpha, t), 0);
+                H[j + 1] = h1;
+                hdiag = hold;
+            }
+            best = __builtin_elementwise_max(__builtin_elementwise_max(best, h0), h1);
+        }
+    }
+    hout = H[T - 1];
+    fout = f;
+}
+
+template <int T, int W>
+__global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
+    constexpr int PW = 64 * T;          // query columns per pass
+    constexpr int RS = PW + 8;          // int16 per profile row (padded)
+    extern __shared__ uint32_t lds[];
+    int16_t *prof = (int16_t *)lds;
+    __shared__ int s_item;
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int pad = a.R - 1;
+    int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
+    const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int q = a.item_q[it];
+        const int id = a.item_ids[(size_t)it * W + w];
+        const int64_t n64 = id >= 0 ? a.off[id + 1] - a.off[id] : 0;
+        const int n = (int)n64;
+        const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
+        const int mp = a.qs.mpad[q];
+        const int npass = (a.qs.qlen[q] + PW - 1) / PW;
+        const int8_t *qp = a.qs.qp + a.qs.qp_off[q];
+        int best = 0;
+
+        for (int p = 0; p < npass; ++p) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
+                const int r = e / PW, c = e - r * PW;
+                const int col = p * PW + c;
+                prof[r * RS + c] = col < mp ? (int16_t)qp[(size_t)r * mp + col] : (int16_t)0;
+            }
+            __syncthreads();
+            if (n <= 0) continue;
+
+            const bool has_in = p > 0, has_out = p + 1 < npass;
+            const int nblk = (n + 63) / 64;
+            const int steps = has_out ? nblk * 64 + 63 : n + 63;
+            int H[T], E[T];
+#pragma unroll
+            for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
+            int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
+            // Feeders: lane k holds the data of subject row 64*b + k; lane 0's
+            // value is consumed each step, then the feeder shifts down a lane.
+            int fR, fH, fF, nR, nH, nF;
+            {
+                const int row = lane;
+                fR = row < n ? s[row] : pad;
+                fH = (has_in && row < n) ? wsc[2 * row] : 0;
+                fF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+                const int row2 = 64 + lane;
+                nR = row2 < n ? s[row2] : pad;
+                nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
+                nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
+            }
+            for (int t = 0; t < steps; ++t) {
+                if (t > 0 && (t & 63) == 0) {
+                    fR = nR; fH = nH; fF = nF;
+                    const int row = t + 64 + lane;
+                    nR = row < n ? s[row] : pad;
+                    nH = (has_in && row < n) ? wsc[2 * row] : 0;
+                    nF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+                }
+                r = shr1(fR, r);
+                const int hin = shr1(fH, hout);
+                const int fin = shr1(fF, fout);
+                fR = shl1(fR, fR);
+                fH = shl1(fH, fH);
+                fF = shl1(fF, fF);
+                const uint2 *pr = (const uint2 *)(prof + r * RS + lane * T);
+                intra_row<T>(H, E, pr, hb_prev, fin, a.alpha, a.beta, best, hout, fout);
+                hb_prev = hin;
+                if (has_out) {
+                    cH = shl1(hout, cH);
+                    cF = shl1(fout, cF);
+                    if ((t & 63) == 62 && t >= 126) {
+                        const int row = t - 126 + lane;
+                        wsc[2 * row] = cH;
+                        wsc[2 * row + 1] = cF;
+                    }
+                }
+            }
+        }
+        if (id >= 0) {
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+            if (lane == 0) a.scores[(size_t)q * a.n_seqs + id] = best;
+        }
+    }
+}
+
+int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
+
+template <int T, int W>
+static hipError_t launch_intra_t(const IntraArgs &a, int grid, hipStream_t st) {
+    const int lds = intra_lds_bytes(a.R, T);
+    hipError_t e = hipFuncSetAttribute((const void *)intra_kernel<T, W>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((intra_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st) {
+#define SWMI_INTRA_CASE(T_, W_) \
+    if (T == T_ && waves == W_) return launch_intra_t<T_, W_>(a, grid, st);
+    SWMI_INTRA_CASE(4, 1) SWMI_INTRA_CASE(8, 1) SWMI_INTRA_CASE(16, 1)
+    SWMI_INTRA_CASE(4, 4) SWMI_INTRA_CASE(8, 4) SWMI_INTRA_CASE(16, 4)
+#undef SWMI_INTRA_CASE
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Utilities and top-k (stage iv: scores in descending order; equal scores by
+// ascending database index).  Exact radix select over the 32-bit scores in
+// four 8-bit passes, then an ordered gather of the ties at the threshold.
+// ---------------------------------------------------------------------------
+__global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+__global__ void topk_init(int32_t *state, uint32_t *hist, int32_t k) {
+    const int q = blockIdx.x;
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[q * 256 + b] = 0;
+    if (threadIdx.x == 0) {
+        state[q * 4 + 0] = 0;   // prefix of the threshold found so far
+        state[q * 4 + 1] = k;   // entries still needed at or below the prefix
+        state[q * 4 + 2] = 0;   // entries strictly above the threshold
+        state[q * 4 + 3] = 0;   // write cursor of those entries
+    }
+}
+
+__global__ void topk_hist(const int32_t *scores, int64_t n, int pass, const int32_t *state,
+                          uint32_t *hist) {
+    __shared__ uint32_t h[256];
+    const int q = blockIdx.y;
+    for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const uint32_t prefix = (uint32_t)state[q * 4 + 0];
+    const int shift = 24 - 8 * pass;
+    const int32_t *row = scores + (size_t)q * n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)row[i];
+        if (pass == 0 || (v >> (shift + 8)) == prefix) atomicAdd(&h[(v >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 256; b += blockDim.x)
+        if (h[b]) atomicAdd(&hist[q * 256 + b], h[b]);
+}
+
+__global__ void topk_select(int32_t *state, uint32_t *hist, int nq) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    uint32_t *h = hist + q * 256;
+    const int64_t kleft = state[q * 4 + 1];
+    int64_t cum = 0, above = -1;
+    int chosen = 0;
+    for (int b = 255; b >= 0; --b) {
+        if (above < 0 && cum + h[b] >= kleft) {
+            chosen = b;
+            above = cum;
+        }
+        cum += h[b];
+    }
+    if (above < 0) above = cum - h[0];   // fewer entries than k: take all
+    state[q * 4 + 0] = (int32_t)(((uint32_t)state[q * 4 + 0] << 8) | (uint32_t)chosen);
+    state[q * 4 + 1] = (int32_t)(kleft - above);
+    state[q * 4 + 2] += (int32_t)above;
+    for (int b = 0; b < 256; ++b) h[b] = 0;
+}
+
+__global__ void topk_gather(const int32_t *scores, int64_t n, int32_t *state, int32_t *eqcnt,
+                            int32_t *cs, int32_t *ci, int32_t k) {
+    __shared__ int32_t red[32];
+    const int q = blockIdx.y;
+    const uint32_t theta = (uint32_t)state[q * 4 + 0];
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const int32_t *row = scores + (size_t)q * n;
+    int cnt = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const uint32_t v = (uint32_t)row[i];
+        if (v > theta) {
+            const int pos = atomicAdd(&state[q * 4 + 3], 1);
+            if (pos < k) {
+                cs[q * k + pos] = (int32_t)v;
+                ci[q * k + pos] = (int32_t)i;
+            }
+        } else if (v == theta) {
+            ++cnt;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+        eqcnt[q * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ void topk_gather_eq(const int32_t *scores, int64_t n, const int32_t *state,
+                               const int32_t *eqcnt, int32_t *cs, int32_t *ci, int32_t k) {
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t s_base;
+    const int q = blockIdx.y;
+    const uint32_t theta = (uint32_t)state[q * 4 + 0];
+    const int need = state[q * 4 + 1];
+    const int cnt_gt = state[q * 4 + 2];
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (unsigned b = 0; b < blockIdx.x; ++b) s += eqcnt[q * gridDim.x + b];
+        s_base = s;
+    }
+    __syncthreads();
+    int base = s_base;
+    if (base >= need) return;
+    const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < n ? lo + chunk : n;
+    const int32_t *row = scores + (size_t)q * n;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int64_t t0 = lo; t0 < hi; t0 += blockDim.x) {
+        const int64_t i = t0 + threadIdx.x;
+        const bool hit = i < hi && (uint32_t)row[i] == theta;
+        const uint64_t bal = __ballot(hit);
+        const int below = __popcll(bal & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+        if (lane == 0) wsum[wv] = __popcll(bal);
+        __syncthreads();
+        int woff = 0, tot = 0;
+        for (int x = 0; x < nw; ++x) {
+            if (x < wv) woff += wsum[x];
+            tot += wsum[x];
+        }
+        const int rank = base + woff + below;
+        if (hit && rank < need) {
+            cs[q * k + cnt_gt + rank] = (int32_t)theta;
+            ci[q * k + cnt_gt + rank] = (int32_t)i;
+        }
+        base += tot;
+        __syncthreads();
+        if (base >= need) break;
+    }
+}
+
+__global__ void topk_final(const int32_t *state, const int32_t *eqcnt, int nblk,
+                           const int32_t *cs, const int32_t *ci, int32_t k, int32_t *top_s,
+                           int64_t *top_i) {
+    extern __shared__ int32_t sm[];
+    int32_t *ks = sm, *ki = sm + k;
+    __shared__ int32_t s_cnt;
+    const int q = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int eq = 0;
+        for (int b = 0; b < nblk; ++b) eq += eqcnt[q * nblk + b];
+        const int need = state[q * 4 + 1];
+        int c = state[q * 4 + 2] + (eq < need ? eq : need);
+        s_cnt = c < k ? c : k;
+    }
+    __syncthreads();
+    const int cnt = s_cnt;
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+        ks[x] = cs[q * k + x];
+        ki[x] = ci[q * k + x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < cnt; x += blockDim.x) {
+        const int sx = ks[x], ix = ki[x];
+        int rank = 0;
+        for (int y = 0; y < cnt; ++y)
+            rank += (ks[y] > sx) || (ks[y] == sx && ki[y] < ix);
+        top_s[(size_t)q * k + rank] = sx;
+        top_i[(size_t)q * k + rank] = ix;
+    }
+    for (int x = cnt + threadIdx.x; x < k; x += blockDim.x) {
+        top_s[(size_t)q * k + x] = -1;
+        top_i[(size_t)q * k + x] = -1;
+    }
+}
+
+hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, int32_t k,
+                       const TopkWork &w, int32_t *top_s, int64_t *top_i, hipStream_t st) {
+    if (nq <= 0) return hipSuccess;
+    hipLaunchKernelGGL(topk_init, dim3(nq), dim3(256), 0, st, w.state, w.hist, k);
+    int64_t hb = (n + 2047) / 2048;
+    if (hb < 1) hb = 1;
+    if (hb > 128) hb = 128;
+    for (int pass = 0; pass < 4; ++pass) {
+        hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb, nq), dim3(256), 0, st, scores, n, pass,
+                           w.state, w.hist);
+        hipLaunchKernelGGL(topk_select, dim3((nq + 63) / 64), dim3(64), 0, st, w.state, w.hist, nq);
+    }
+    hipLaunchKernelGGL(topk_gather, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n, w.state,
+                       w.eqcnt, w.cand_s, w.cand_i, k);
+    hipLaunchKernelGGL(topk_gather_eq, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n,
+                       w.state, w.eqcnt, w.cand_s, w.cand_i, k);
+    hipLaunchKernelGGL(topk_final, dim3(nq), dim3(256), (size_t)k * 8, st, w.state, w.eqcnt,
+                       kTopkBlocks, w.cand_s, w.cand_i, k, top_s, top_i);
+    return hipGetLastError();
+}
+
+}  // namespace swmi

@@ -1,0 +1,275 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Scores are int32 and unique per (query, subject), and the top-k order is
+unique under (score desc, index asc), so every comparison is exact equality.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthdata as sd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def swmi():
+    import paper_1404_4152_amd as p
+    p.lib()
+    return p
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return oracle.load()
+
+
+def random_db(rng, n, A, lo, hi, zero_every=0):
+    lens = rng.integers(lo, hi + 1, size=n)
+    if zero_every:
+        lens[::zero_every] = 0
+    seqs = [rng.integers(0, A, size=int(L)).astype(np.uint8) for L in lens]
+    return sd.pack_sequences(seqs)
+
+
+def expect_equal(got, exp, what=""):
+    got = np.asarray(got)
+    exp = np.asarray(exp)
+    bad = np.flatnonzero(got != exp)
+    assert bad.size == 0, (f"{what}: {bad.size} mismatches, first at {bad[:5].tolist()}: "
+                           f"got {got[bad[:5]].tolist()} expected {exp[bad[:5]].tolist()}")
+
+
+QLENS = [1, 7, 63, 64, 65, 130, 200, 513, 1100]
+
+
+@pytest.mark.parametrize("route", [-1, 1, 0])
+def test_random_db_all_routes(swmi, orc, route):
+    rng = np.random.Generator(np.random.PCG64(100 + route))
+    A = 20
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 700, A, 0, 400, zero_every=37)
+    db = swmi.Database(res, off, A, long_threshold=route)
+    try:
+        for L in QLENS:
+            q = sd.random_residues(rng, L)
+            print(f"route={route} qlen={L}", flush=True)
+            expect_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12),
+                         f"route {route} qlen {L}")
+    finally:
+        db.close()
+
+
+@pytest.mark.parametrize("tier,strip,waves", [(1, 16, 4), (1, 16, 8), (1, 32, 4), (1, 32, 6),
+                                              (1, 32, 8), (1, 64, 4), (2, 16, 4), (2, 32, 8),
+                                              (2, 64, 4)])
+def test_inter_plans(swmi, orc, tier, strip, waves):
+    rng = np.random.Generator(np.random.PCG64(7 * strip + waves + tier))
+    A = 20
+    M = sd.blosum_style_matrix()
+    # more than 128 * waves subjects so several work items and a ragged last group
+    res, off = random_db(rng, 128 * waves * 2 + 77, A, 1, 260, zero_every=53)
+    db = swmi.Database(res, off, A, long_threshold=-1)
+    try:
+        db.set_opts(tier=tier, strip=strip, waves=waves)
+        for L in [5, strip, strip + 1, 3 * strip + 7, 300]:
+            q = sd.random_residues(rng, L)
+            print(f"tier={tier} strip={strip} waves={waves} qlen={L}", flush=True)
+            expect_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12),
+                         f"plan {tier}/{strip}/{waves} qlen {L}")
+            st = db.stats()
+            assert st["tier"] == tier and st["strip"] == strip
+    finally:
+        db.close()
+
+
+@pytest.mark.parametrize("A,alpha,beta", [(1, 0, 0), (2, 1, 1), (4, 0, 5), (7, 3, 3), (24, 1, 11),
+                                          (32, 2, 12), (20, 0, 0), (20, 5, 40), (20, 2, 5000)])
+def test_alphabets_and_penalties(swmi, orc, A, alpha, beta):
+    rng = np.random.Generator(np.random.PCG64(A * 1000 + beta))
+    M = sd.random_matrix(rng, A, -6, 9)
+    res, off = random_db(rng, 300, A, 0, 300, zero_every=29)
+    for route in (-1, 1):
+        db = swmi.Database(res, off, A, long_threshold=route)
+        try:
+            for L in [1, 40, 150]:
+                q = sd.uniform_residues(rng, L, A)
+                print(f"A={A} alpha={alpha} beta={beta} route={route} qlen={L}", flush=True)
+                expect_equal(db.search(q, M, alpha, beta), orc.search(q, res, off, M, alpha, beta),
+                             f"A={A} a={alpha} b={beta} route={route} L={L}")
+        finally:
+            db.close()
+
+
+def test_asymmetric_matrix_orientation(swmi, orc):
+    M = np.array([[0, 5], [-3, 0]], np.int8)
+    res, off = sd.pack_sequences([np.array([1], np.uint8), np.array([0], np.uint8)])
+    for route in (-1, 1):
+        db = swmi.Database(res, off, 2, long_threshold=route)
+        try:
+            got = db.search(np.array([0], np.uint8), M, 1, 3)
+            assert got.tolist() == [5, 0]
+        finally:
+            db.close()
+
+
+@pytest.mark.parametrize("tier", [1, 2])
+def test_forced_overflow_recompute(swmi, orc, tier):
+    """A lowered threshold flags many lanes; the int32 recompute keeps every score exact."""
+    rng = np.random.Generator(np.random.PCG64(31 + tier))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 1500, 20, 1, 300, zero_every=41)
+    db = swmi.Database(res, off, 20, long_threshold=-1)
+    try:
+        db.set_opts(tier=tier, sat_threshold=20)
+        for L in [33, 250, 700]:
+            q = sd.random_residues(rng, L)
+            print(f"forced overflow tier={tier} qlen={L}", flush=True)
+            exp = orc.search(q, res, off, M, 2, 12)
+            expect_equal(db.search(q, M, 2, 12), exp, f"forced overflow L={L}")
+            st = db.stats()
+            assert st["recomputed_pairs"] == int((exp >= 20).sum())
+    finally:
+        db.close()
+
+
+def test_planted_homologs_exceed_narrow_tiers(swmi, orc):
+    """Scores above 1920 (fp16 tier) and above 32767 (int16 tier) stay exact."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    A = 20
+    M = sd.blosum_style_matrix().copy()
+    M[17, 17] = 110         # a residue whose self score makes long identical runs huge
+    q_long = sd.random_residues(rng, 900)
+    q_long[::2] = 17        # self score > 32767
+    q_mid = sd.random_residues(rng, 500)
+    res, off = random_db(rng, 600, A, 1, 400)
+    res, off = sd.plant_homologs(res, off, [q_long, q_mid, q_long],
+                                 where=[10, 200, 599], identity=0.9)
+    assert orc.sw_score(q_long, res[off[10]:off[11]], M, 2, 12) > 32767
+    assert 1920 < orc.sw_score(q_mid, res[off[200]:off[201]], M, 2, 12) < 32767
+    for tier in (1, 2):
+        for route in (-1, 1):
+            db = swmi.Database(res, off, A, long_threshold=route)
+            try:
+                db.set_opts(tier=tier)
+                for q in (q_long, q_mid):
+                    print(f"planted tier={tier} route={route} qlen={len(q)}", flush=True)
+                    exp = orc.search(q, res, off, M, 2, 12)
+                    got = db.search(q, M, 2, 12)
+                    expect_equal(got, exp, f"planted tier {tier} route {route}")
+            finally:
+                db.close()
+
+
+@pytest.mark.parametrize("k", [1, 10, 100, 613])
+def test_topk_with_heavy_ties(swmi, orc, k):
+    rng = np.random.Generator(np.random.PCG64(k))
+    A = 3
+    M = np.array([[2, -1, -1], [-1, 2, -1], [-1, -1, 2]], np.int8)
+    res, off = random_db(rng, 600, A, 0, 12)
+    q = sd.uniform_residues(rng, 10, A)
+    for route in (-1, 1):
+        db = swmi.Database(res, off, A, long_threshold=route)
+        try:
+            ts, ti = db.topk(q, M, 1, 2, k)
+            es, ei = oracle.topk(orc.search(q, res, off, M, 1, 2), k)
+            expect_equal(ts, es, "topk scores")
+            expect_equal(ti, ei, "topk indices")
+        finally:
+            db.close()
+
+
+def test_batch_matches_single_queries(swmi, orc):
+    rng = np.random.Generator(np.random.PCG64(77))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 2000, 20, 0, 500, zero_every=97)
+    qs = [sd.random_residues(rng, int(L)) for L in [1, 50, 64, 65, 300, 701, 1500]]
+    db = swmi.Database(res, off, 20, long_threshold=-1)
+    try:
+        ts, ti, al = db.search_batch(qs, M, 2, 12, 10, all_scores=True)
+        for x, q in enumerate(qs):
+            exp = orc.search(q, res, off, M, 2, 12)
+            expect_equal(al[x], exp, f"batch all_scores q{x}")
+            es, ei = oracle.topk(exp, 10)
+            expect_equal(ts[x], es, f"batch topk scores q{x}")
+            expect_equal(ti[x], ei, f"batch topk idx q{x}")
+    finally:
+        db.close()
+
+
+def test_repeat_runs_identical(swmi):
+    """Races would show up as run-to-run differences."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 5000, 20, 1, 600)
+    q = sd.random_residues(rng, 333)
+    db = swmi.Database(res, off, 20, long_threshold=-1)
+    try:
+        first = db.search(q, M, 2, 12)
+        for _ in range(3):
+            assert np.array_equal(db.search(q, M, 2, 12), first)
+    finally:
+        db.close()
+
+
+def test_edge_databases(swmi, orc):
+    M = sd.blosum_style_matrix()
+    q = sd.make_queries([70])[0]
+    # every subject empty
+    res, off = sd.pack_sequences([np.zeros(0, np.uint8)] * 5)
+    for route in (-1, 1, 0):
+        db = swmi.Database(res, off, 20, long_threshold=route)
+        try:
+            assert db.search(q, M, 2, 12).tolist() == [0] * 5
+            ts, ti = db.topk(q, M, 2, 12, 7)
+            assert ts.tolist() == [0] * 5 + [-1, -1] and ti.tolist() == [0, 1, 2, 3, 4, -1, -1]
+        finally:
+            db.close()
+    # a single one-residue subject
+    res, off = sd.pack_sequences([np.array([3], np.uint8)])
+    db = swmi.Database(res, off, 20)
+    try:
+        assert db.search(q, M, 2, 12).tolist() == orc.search(q, res, off, M, 2, 12).tolist()
+    finally:
+        db.close()
+
+
+def test_invalid_search_arguments(swmi):
+    M = sd.blosum_style_matrix()
+    res, off = sd.pack_sequences([np.array([1, 2, 3], np.uint8)])
+    db = swmi.Database(res, off, 20)
+    try:
+        for bad in [dict(alpha=-1, beta=3), dict(alpha=5, beta=4), dict(alpha=1, beta=2 ** 30 + 1)]:
+            with pytest.raises(swmi.SwError) as e:
+                db.search(np.array([1], np.uint8), M, bad["alpha"], bad["beta"])
+            assert e.value.code == swmi.SW_EINVAL
+        with pytest.raises(swmi.SwError):
+            db.search(np.array([25], np.uint8), M, 2, 12)
+        with pytest.raises(swmi.SwError):
+            db.search(np.zeros(0, np.uint8), M, 2, 12)
+        with pytest.raises(swmi.SwError):
+            db.topk(np.array([1], np.uint8), M, 2, 12, 0)
+        with pytest.raises(swmi.SwError):
+            db.search(np.array([1], np.uint8), M[:10, :10], 2, 12)
+    finally:
+        db.close()
+
+
+def test_plain_small_workload(swmi, orc):
+    """1 query of 144 vs 2,000 subjects (log-normal, mean 350, 20..2,000): full parity."""
+    w = sd.WORKLOADS["plain_small"]
+    res, off = w.db()
+    q = w.queries()[0]
+    M = w.matrix()
+    db = swmi.Database(res, off, 20)
+    try:
+        exp = orc.search(q, res, off, M, w.alpha, w.beta)
+        expect_equal(db.search(q, M, w.alpha, w.beta), exp, "plain_small")
+        ts, ti = db.topk(q, M, w.alpha, w.beta, 10)
+        es, ei = oracle.topk(exp, 10)
+        expect_equal(ts, es, "plain_small topk")
+        expect_equal(ti, ei, "plain_small topk idx")
+    finally:
+        db.close()
