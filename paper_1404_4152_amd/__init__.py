@@ -14,7 +14,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libswmi.so")
+LIB_PATH = os.environ.get("SWMI_LIB") or os.path.join(HERE, "libswmi.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EBUSY, SW_ENOTFOUND, SW_ESTOPPED = 0, -1, -2, -3, -4, -5, -6
 SW_TIER_AUTO, SW_TIER_F16X2, SW_TIER_I16X2 = 0, 1, 2

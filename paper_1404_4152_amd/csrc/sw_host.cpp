@@ -117,7 +117,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 struct Plan {
     int tier = TIER_F16X2;
     int strip = 32;
-    int waves = 8;
+    int waves = 4;
     int thr = kThrF16;
 };
 

@@ -131,17 +131,21 @@ struct Strip {
     typedef Lane<TIER> L;
     typedef typename L::V V;
 
-    // One subject row across the strip.  P: the row's pair-profile values.
+    // One subject row across the strip.  P holds this row's pair-profile
+    // values; each 4-column slot is refilled with the next row's values
+    // (`nxt`) as soon as it has been consumed, so the LDS latency hides behind
+    // a full row of arithmetic with only T/4 uint4 registers.
     // hb_prev = H(i-1, j0-1), fin = F(i, j0).  Returns H(i, j0+T-1), F(i, j0+T).
     static __device__ __forceinline__ void row(const L &ops, V (&H)[T], V (&E)[T],
-                                               const uint4 (&P)[T / 4], uint32_t hb_prev,
-                                               uint32_t fin, V &best, uint32_t &hout,
-                                               uint32_t &fout) {
+                                               uint4 (&P)[T / 4], const uint4 *nxt,
+                                               uint32_t hb_prev, uint32_t fin, V &best,
+                                               uint32_t &hout, uint32_t &fout) {
         V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) {
             const uint32_t pv[4] = {P[j4].x, P[j4].y, P[j4].z, P[j4].w};
+            P[j4] = nxt[j4];
 #pragma unroll
             for (int u = 0; u < 4; u += 2) {
                 const int j = j4 * 4 + u;
@@ -177,23 +181,76 @@ struct Strip {
         asm volatile("" : "+v"(best));
     }
 
-    static __device__ __forceinline__ void load(uint4 (&P)[T / 4], const uint32_t *lds, int RS,
-                                                uint32_t code) {
-        const uint4 *src = (const uint4 *)(lds + code * RS);
+    // All rows of one group against one strip.  HAS_IN: read the boundary
+    // column left by the previous strip; HAS_OUT: write it for the next.
+    // Every load is unconditional (addresses clamp at the last chunk) so the
+    // compiler can count outstanding loads instead of draining them.
+    template <bool HAS_IN, bool HAS_OUT>
+    static __device__ __forceinline__ void pass(const L &ops, V &best, const uint16_t *codes,
+                                                uint32_t *wsc, int nch, const uint32_t *lds,
+                                                int RS) {
+        V H[T], E[T];
 #pragma unroll
-        for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+        for (int j = 0; j < T; ++j) { H[j] = L::zero(); E[j] = L::zero(); }
+        uint32_t hb_prev = 0;
+        const int last = nch - 1;
+        uint2 cd = *(const uint2 *)codes;
+        uint2 cd_n = *(const uint2 *)(codes + (size_t)(last < 1 ? last : 1) * 256);
+        uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+        if (HAS_IN) {
+            b0 = ((const uint4 *)wsc)[0];
+            b1 = ((const uint4 *)wsc)[1];
+        }
+        uint4 P[T / 4];
+        {
+            const uint4 *src = (const uint4 *)(lds + (cd.x & 0xffffu) * RS);
+#pragma unroll
+            for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+        }
+        for (int c = 0; c < nch; ++c) {
+            const int c1 = c + 1 < last ? c + 1 : last;
+            const int c2 = c + 2 < last ? c + 2 : last;
+            const uint2 cd_nn = *(const uint2 *)(codes + (size_t)c2 * 256);
+            uint4 b0n = make_uint4(0, 0, 0, 0), b1n = make_uint4(0, 0, 0, 0);
+            if (HAS_IN) {
+                b0n = ((const uint4 *)(wsc + (size_t)c1 * 512))[0];
+                b1n = ((const uint4 *)(wsc + (size_t)c1 * 512))[1];
+            }
+            const uint4 *n1 = (const uint4 *)(lds + (cd.x >> 16) * RS);
+            const uint4 *n2 = (const uint4 *)(lds + (cd.y & 0xffffu) * RS);
+            const uint4 *n3 = (const uint4 *)(lds + (cd.y >> 16) * RS);
+            const uint4 *n4 = (const uint4 *)(lds + (cd_n.x & 0xffffu) * RS);
+            uint32_t o[8];
+            row(ops, H, E, P, n1, hb_prev, b0.y, best, o[0], o[1]);
+            hb_prev = b0.x;
+            row(ops, H, E, P, n2, hb_prev, b0.w, best, o[2], o[3]);
+            hb_prev = b0.z;
+            row(ops, H, E, P, n3, hb_prev, b1.y, best, o[4], o[5]);
+            hb_prev = b1.x;
+            row(ops, H, E, P, n4, hb_prev, b1.w, best, o[6], o[7]);
+            hb_prev = b1.z;
+            if (HAS_OUT) {
+                uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
+                dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+                dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+            }
+            cd = cd_n;
+            cd_n = cd_nn;
+            b0 = b0n;
+            b1 = b1n;
+        }
     }
 };
 
 // Occupancy the register budget is sized for (waves per SIMD).
-template <int T> struct InterOcc { static constexpr int value = T <= 16 ? 3 : (T <= 32 ? 2 : 1); };
+template <int T> struct InterOcc { static constexpr int value = T <= 16 ? 4 : (T <= 32 ? 2 : 1); };
 
 template <int T, int W, int TIER>
 __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(InterArgs a, int magic) {
     typedef Lane<TIER> L;
     typedef typename L::V V;
     constexpr int RS = T + 4;                 // dwords per pair-profile row (padded)
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const int R = a.R;
     const int RR = R * R;
     uint32_t *stage = lds + RR * RS;          // R x T/2 dwords: the strip's profile, 16-bit
@@ -239,61 +296,14 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
             __syncthreads();
             if (!active) continue;
 
-            V H[T], E[T];
-#pragma unroll
-            for (int j = 0; j < T; ++j) { H[j] = L::zero(); E[j] = L::zero(); }
-            uint32_t hb_prev = 0;
-            const bool has_in = k > 0, has_out = k + 1 < nstrips;
             const int nch = rows / kChunk;
-            // Pair codes are fetched two chunks ahead, boundary columns one chunk
-            // ahead, and the profile row of the next subject row while the
-            // current one computes.
-            uint2 cd = *(const uint2 *)codes;
-            uint2 cd_n = nch > 1 ? *(const uint2 *)(codes + 256) : cd;
-            uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
-            if (has_in) {
-                b0 = ((const uint4 *)wsc)[0];
-                b1 = ((const uint4 *)wsc)[1];
-            }
-            uint4 P0[T / 4], P1[T / 4];
-            Strip<T, TIER>::load(P0, lds, RS, cd.x & 0xffffu);
-            for (int c = 0; c < nch; ++c) {
-                const uint2 cd_nn = c + 2 < nch ? *(const uint2 *)(codes + (size_t)(c + 2) * 256) : cd_n;
-                uint4 b0n = make_uint4(0, 0, 0, 0), b1n = make_uint4(0, 0, 0, 0);
-                if (has_in && c + 1 < nch) {
-                    b0n = ((const uint4 *)(wsc + (size_t)(c + 1) * 512))[0];
-                    b1n = ((const uint4 *)(wsc + (size_t)(c + 1) * 512))[1];
-                }
-                uint32_t out[8];
-                Strip<T, TIER>::load(P1, lds, RS, cd.x >> 16);
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::row(ops, H, E, P0, hb_prev, b0.y, best, out[0], out[1]);
-                hb_prev = b0.x;
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::load(P0, lds, RS, cd.y & 0xffffu);
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::row(ops, H, E, P1, hb_prev, b0.w, best, out[2], out[3]);
-                hb_prev = b0.z;
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::load(P1, lds, RS, cd.y >> 16);
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::row(ops, H, E, P0, hb_prev, b1.y, best, out[4], out[5]);
-                hb_prev = b1.x;
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::load(P0, lds, RS, cd_n.x & 0xffffu);
-                __builtin_amdgcn_sched_barrier(0);
-                Strip<T, TIER>::row(ops, H, E, P1, hb_prev, b1.w, best, out[6], out[7]);
-                hb_prev = b1.z;
-                __builtin_amdgcn_sched_barrier(0);
-                if (has_out) {
-                    uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
-                    dst[0] = make_uint4(out[0], out[1], out[2], out[3]);
-                    dst[1] = make_uint4(out[4], out[5], out[6], out[7]);
-                }
-                cd = cd_n;
-                cd_n = cd_nn;
-                b0 = b0n;
-                b1 = b1n;
+            typedef Strip<T, TIER> S;
+            if (k == 0) {
+                if (nstrips == 1) S::template pass<false, false>(ops, best, codes, wsc, nch, lds, RS);
+                else S::template pass<false, true>(ops, best, codes, wsc, nch, lds, RS);
+            } else {
+                if (k + 1 == nstrips) S::template pass<true, false>(ops, best, codes, wsc, nch, lds, RS);
+                else S::template pass<true, true>(ops, best, codes, wsc, nch, lds, RS);
             }
         }
         if (active) {
@@ -423,7 +433,7 @@ template <int T, int W>
 __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // int16 per profile row (padded)
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int16_t *prof = (int16_t *)lds;
     __shared__ int s_item;
 
@@ -684,7 +694,7 @@ __global__ void topk_gather_eq(const int32_t *scores, int64_t n, const int32_t *
 __global__ void topk_final(const int32_t *state, const int32_t *eqcnt, int nblk,
                            const int32_t *cs, const int32_t *ci, int32_t k, int32_t *top_s,
                            int64_t *top_i) {
-    extern __shared__ int32_t sm[];
+    extern __shared__ __attribute__((aligned(16))) int32_t sm[];
     int32_t *ks = sm, *ki = sm + k;
     __shared__ int32_t s_cnt;
     const int q = blockIdx.x;
