@@ -32,6 +32,21 @@ PEAK_HALF_OPS = 2 * PEAK_LANE_OPS                    # packed 16-bit lane-ops/s 
 OPS_PER_CELL = 7.5                                   # add, max3, sub, 2x(sub+max3), max3/2
 
 
+def measured_traffic(workload, plan_overridden):
+    """HBM bytes per launch of the lane-per-subject kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter passes, if they were taken on this exact
+    kernel source and workload; None otherwise."""
+    import hashlib
+    rec_path = os.path.join(ROOT, "profiles", f"inter_kernel_{workload}_traffic.json")
+    src = os.path.join(ROOT, "paper_1404_4152_amd", "csrc", "sw_kernels.hip")
+    if plan_overridden or not os.path.exists(rec_path):
+        return None
+    rec = json.load(open(rec_path))
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -154,8 +169,10 @@ def main():
     ops_per_launch = OPS_PER_CELL * inter_cells / len(per_query)
     achieved = ops_per_launch / (avg_launch_ms / 1e3) / 1e12
     peak = PEAK_HALF_OPS / 1e12
+    traffic = measured_traffic(w.name, bool(args.tier or args.strip or args.waves))
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
-                "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "unit": "Tops/s", "frac": round(achieved / peak, 4),
+                "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes per launch",
                 "kernel": "inter_kernel (f16x2)", "ops_per_cell": OPS_PER_CELL,
                 "avg_launch_ms": round(avg_launch_ms, 3)}
     out = {
