@@ -85,7 +85,10 @@ typedef struct sw_search_opts {
     int32_t waves;          /* waves per workgroup of the lane-per-subject kernel: 4, 6, 8 */
     int32_t sat_threshold;  /* test knob: if > 0, a narrow-tier lane whose best score reaches
                                min(this, tier ceiling) is flagged and recomputed in int32 */
-    int32_t reserved[4];
+    int32_t graph;          /* sw_db_search_batch: 0 = capture the device work of a batch shape in
+                               a HIP graph and replay it on later calls of that shape, -1 = launch
+                               eagerly every time */
+    int32_t reserved[3];
 } sw_search_opts;
 
 /* Statistics of the last search call on a database handle. */
@@ -97,11 +100,12 @@ typedef struct sw_stats {
     int64_t intra_pairs;      /* pairs evaluated by the wave-per-pair kernel */
     double  kernel_ms;        /* device time of the alignment kernels (HIP events) */
     double  total_ms;         /* wall time of the whole call */
-    double  inter_ms;         /* device time of the lane-per-subject kernel alone */
+    double  inter_ms;         /* device time of the lane-per-subject kernel alone (-1 when the
+                                 work ran as a graph, which is timed as a whole) */
     int32_t tier;             /* tier used */
     int32_t strip;            /* strip width used */
     int32_t waves;            /* waves per workgroup used */
-    int32_t reserved;
+    int32_t graphed;          /* 1 if the device work ran as a captured HIP graph */
 } sw_stats;
 
 /* Open a database (section III, stage ii: sequences are sorted by length and
@@ -191,7 +195,9 @@ int sw_server_submit(sw_server *srv, const uint8_t *query, int32_t qlen, const s
 int sw_server_wait(sw_server *srv, uint64_t ticket, int32_t *top_scores, int64_t *top_idx,
                    sw_req_stats *stats);
 
-/* Stop the server: pending requests fail with SW_ESTOPPED.  NULL is ignored. */
+/* Stop the server: requests not yet complete fail with SW_ESTOPPED; threads
+ * blocked in sw_server_wait return before this call does.  No sw_server_* call
+ * may use the handle afterwards.  NULL is ignored. */
 void sw_server_stop(sw_server *srv);
 
 /* Message for the last failed call on this thread ("" if none). */

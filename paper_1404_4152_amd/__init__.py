@@ -40,7 +40,8 @@ class sw_db_opts(ctypes.Structure):
 
 class sw_search_opts(ctypes.Structure):
     _fields_ = [("tier", ctypes.c_int32), ("strip", ctypes.c_int32), ("waves", ctypes.c_int32),
-                ("sat_threshold", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("sat_threshold", ctypes.c_int32), ("graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class sw_stats(ctypes.Structure):
@@ -48,7 +49,7 @@ class sw_stats(ctypes.Structure):
                 ("inter_cells", ctypes.c_int64), ("recomputed_pairs", ctypes.c_int64), ("intra_pairs", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("inter_ms", ctypes.c_double), ("tier", ctypes.c_int32), ("strip", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("graphed", ctypes.c_int32)]
 
 
 class sw_server_opts(ctypes.Structure):
@@ -159,10 +160,10 @@ def sw_db_size(h) -> int:
     return int(lib().sw_db_size(h))
 
 
-def sw_db_set_opts(h, tier=0, strip=0, waves=0, sat_threshold=0, reset=False):
+def sw_db_set_opts(h, tier=0, strip=0, waves=0, sat_threshold=0, graph=0, reset=False):
     if reset:
         return _check(lib().sw_db_set_opts(h, None))
-    o = sw_search_opts(tier, strip, waves, sat_threshold)
+    o = sw_search_opts(tier, strip, waves, sat_threshold, graph)
     return _check(lib().sw_db_set_opts(h, ctypes.byref(o)))
 
 

@@ -11,6 +11,9 @@
 // Search (stages i and iv): build the query profile (section III.B.2; row r
 // holds the scores of the whole query against residue r), run the kernels,
 // recompute flagged narrow-tier pairs exactly, then sort or select the scores.
+// Batches of queries share one persistent launch (captured once per shape in
+// a HIP graph); the server keeps the database resident and coalesces the
+// requests in flight into shared passes over database chunks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,16 +59,27 @@ int fail(int code, const char *fmt, ...) {
             return fail(SW_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
 
+#define TRY(expr)                     \
+    do {                              \
+        int rc_ = (expr);             \
+        if (rc_ != SW_OK) return rc_; \
+    } while (0)
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(
                std::chrono::steady_clock::now().time_since_epoch())
         .count();
 }
 
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
 // Grow-only device buffer.
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
     ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
@@ -93,6 +107,9 @@ struct DevBuf {
 struct HostBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
     ~HostBuf() {
         if (p) (void)hipHostFree(p);
     }
@@ -112,13 +129,38 @@ struct HostBuf {
     template <class T> T *as() const { return (T *)p; }
 };
 
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
 struct Plan {
     int tier = TIER_F16X2;
     int strip = 32;
     int waves = 4;
     int thr = kThrF16;
+};
+
+constexpr int kIntraWaves = 4;   // waves per workgroup of the wave-per-pair kernel (long list)
+
+int intra_T_for(int64_t max_qlen) {
+    if (max_qlen <= 256) return 4;
+    if (max_qlen <= 512) return 8;
+    return 16;
+}
+
+int qlen_bucket(int64_t qlen) {
+    int b = 0;
+    while ((64LL << b) < qlen && b < 20) ++b;
+    return b;
+}
+
+// Work item lists of one device pass, built on the host.
+struct Items {
+    std::vector<int32_t> inter_q, inter_g;   // lane-per-subject: (slot, first group of block)
+    std::vector<int32_t> intra_q, intra_ids; // wave-per-pair: (slot, kIntraWaves subject ids)
+};
+
+// Kernels and grids of one pass.
+struct Launch {
+    Plan plan;
+    int Ti = 16;
+    int grid_inter = 0, grid_long = 0, grid_ovf = 0;
 };
 
 }  // namespace
@@ -142,18 +184,21 @@ struct sw_db {
     int64_t long_res = 0;
     int64_t long_threshold = 0;
     // device copies
-    DevBuf d_res, d_off, d_codes, d_grp_base, d_grp_rows, d_grp_ids, d_long_ids;
-    // per-call workspaces
-    DevBuf w_qp, w_qmeta, w_scores, w_items, w_counters, w_ovf, w_scr_inter, w_scr_intra,
-        w_topk, w_top;
+    DevBuf d_res, d_off, d_codes, d_grp_base, d_grp_rows, d_grp_ids;
+    // per-call workspaces (plain and batched searches)
+    DevBuf w_stage, w_scores, w_counters, w_ovf, w_scr_inter, w_scr_intra, w_topk, w_top;
     HostBuf h_stage;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::mutex mu;
     sw_search_opts opts{};
     sw_stats last{};
-    // autotuner table: query-length bucket -> plan
-    std::map<int, Plan> tuned;
+    std::map<int, Plan> tuned;        // autotuner: query-length bucket -> plan
     int cus = 256;
+    std::string signature;
+    // captured batch graph and the key of every argument it was captured with
+    hipGraphExec_t graph = nullptr;
+    std::string graph_key;
+    bool server_attached = false;
 };
 
 namespace {
@@ -171,23 +216,20 @@ int validate_scoring(const sw_db *db, const sw_scoring *sc) {
 }
 
 int validate_query(const sw_db *db, const uint8_t *q, int64_t qlen) {
-    if (qlen < 1 || qlen > SW_MAX_LEN) return fail(SW_EINVAL, "query length %lld not in 1..2^24", (long long)qlen);
+    if (qlen < 1 || qlen > SW_MAX_LEN)
+        return fail(SW_EINVAL, "query length %lld not in 1..2^24", (long long)qlen);
     if (!q) return fail(SW_EINVAL, "query is NULL");
     for (int64_t j = 0; j < qlen; ++j)
         if (q[j] >= db->alphabet)
-            return fail(SW_EINVAL, "query code %d at %lld >= alphabet %d", q[j], (long long)j, db->alphabet);
+            return fail(SW_EINVAL, "query code %d at %lld >= alphabet %d", q[j], (long long)j,
+                        db->alphabet);
     return SW_OK;
 }
 
 Plan plan_for(const sw_db *db, int64_t max_qlen) {
     Plan p;
-    // Autotuned entry for this query-length bucket, if any.
-    if (!db->tuned.empty()) {
-        int bucket = 0;
-        while ((64LL << bucket) < max_qlen && bucket < 20) ++bucket;
-        auto it = db->tuned.find(bucket);
-        if (it != db->tuned.end()) p = it->second;
-    }
+    auto it = db->tuned.find(qlen_bucket(max_qlen));
+    if (it != db->tuned.end()) p = it->second;
     if (db->opts.tier) p.tier = db->opts.tier;
     if (db->opts.strip) p.strip = db->opts.strip;
     if (db->opts.waves) p.waves = db->opts.waves;
@@ -200,262 +242,818 @@ Plan plan_for(const sw_db *db, int64_t max_qlen) {
     return p;
 }
 
-int intra_T_for(int64_t max_qlen) {
-    if (max_qlen <= 256) return 4;
-    if (max_qlen <= 512) return 8;
-    return 16;
+// Query profile (section III.B.2): row r holds the scores of every query
+// position against residue r; the pad row and the columns past the query are 0.
+void write_profile(int8_t *dst, const uint8_t *q, int64_t qlen, int32_t mpad, const sw_scoring *sc,
+                   int R) {
+    const int A = sc->alphabet;
+    for (int r = 0; r < R; ++r) {
+        int8_t *row = dst + (int64_t)r * mpad;
+        if (r < A)
+            for (int64_t j = 0; j < qlen; ++j) row[j] = sc->matrix[q[j] * A + r];
+        else
+            std::memset(row, 0, (size_t)qlen);
+        std::memset(row + qlen, 0, (size_t)(mpad - qlen));
+    }
 }
 
-struct Batch {
-    int32_t nq = 0;
-    std::vector<int64_t> qlen;
-    std::vector<int32_t> mpad;
-    std::vector<int64_t> qp_off;
-    int64_t qp_bytes = 0;
-    int64_t max_qlen = 0;
-    int64_t sum_qlen = 0;
+// Lane-per-subject items for `slots` against group blocks [b0, b1) and, if
+// with_long, wave-per-pair items against the long list; each list longest
+// first (the GPU analogue of the guided schedule of section III.A).
+// stride > 1 keeps every stride-th block only (autotuner sampling).
+void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &slots,
+                 const std::vector<int32_t> &mpad, const std::vector<int64_t> &qlen, int64_t b0,
+                 int64_t b1, bool with_long, int64_t stride, Items &it) {
+    const int W = plan.waves;
+    std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> v;
+    v.reserve((size_t)slots.size() * (size_t)std::max<int64_t>(b1 - b0, 0));
+    for (size_t x = 0; x < slots.size(); ++x) {
+        const int32_t s = slots[x];
+        const int64_t strips = mpad[x] / plan.strip;
+        for (int64_t bk = b0; bk < b1; ++bk) {
+            if (stride > 1 && (bk % stride) != 0) continue;
+            const int last = (int)std::min<int64_t>(db->n_groups, (bk + 1) * W) - 1;
+            v.push_back({(int64_t)db->grp_rows[last] * strips, {s, (int32_t)(bk * W)}});
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    it.inter_q.resize(v.size());
+    it.inter_g.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        it.inter_q[i] = v[i].second.first;
+        it.inter_g[i] = v[i].second.second;
+    }
+    it.intra_q.clear();
+    it.intra_ids.clear();
+    if (!with_long) return;
+    const int64_t nlong = (int64_t)db->long_ids.size();
+    const int64_t nlblk = (nlong + kIntraWaves - 1) / kIntraWaves;
+    std::vector<std::pair<int64_t, std::pair<int32_t, int64_t>>> u;
+    for (size_t x = 0; x < slots.size(); ++x)
+        for (int64_t bk = 0; bk < nlblk; ++bk) {
+            if (stride > 1 && (bk % stride) != 0) continue;
+            u.push_back({db->len[db->long_ids[bk * kIntraWaves]] * qlen[x], {slots[x], bk}});
+        }
+    std::stable_sort(u.begin(), u.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    it.intra_q.resize(u.size());
+    it.intra_ids.resize(u.size() * kIntraWaves);
+    for (size_t i = 0; i < u.size(); ++i) {
+        it.intra_q[i] = u[i].second.first;
+        for (int w = 0; w < kIntraWaves; ++w) {
+            const int64_t x = u[i].second.second * kIntraWaves + w;
+            it.intra_ids[i * kIntraWaves + w] = x < nlong ? db->long_ids[x] : -1;
+        }
+    }
+}
+
+Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_t n_inter,
+                     int64_t n_intra) {
+    Launch L;
+    L.plan = plan;
+    L.Ti = intra_T_for(max_qlen);
+    L.grid_inter = (int)std::min<int64_t>(n_inter, inter_max_grid(db->R, plan.strip, plan.waves));
+    const int per_cu = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, L.Ti) + 64), 8));
+    L.grid_long = (int)std::min<int64_t>(n_intra, (int64_t)per_cu * db->cus);
+    const int per_cu16 = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, 16) + 64), 8));
+    L.grid_ovf = std::min(per_cu16 * db->cus * kIntraWaves, 4096);
+    return L;
+}
+
+int64_t intra_scratch_rows(const sw_db *db) {
+    return round_up(std::max<int64_t>(db->max_len, 1), 64) + 128;
+}
+
+// Device buffers a pass reads and writes.
+struct PassBufs {
+    QuerySet qs{};
+    const int32_t *it_q = nullptr, *it_g = nullptr, *il_q = nullptr, *il_ids = nullptr;
+    int64_t n_inter = 0, n_intra = 0;
+    int32_t *scores = nullptr;
+    int32_t *ovf_q = nullptr, *ovf_id = nullptr;
+    int64_t ovf_cap = 0;
+    int32_t *counters = nullptr;   // inter head, overflow count, long head, recompute head
+    uint32_t *scr_inter = nullptr;
+    int32_t *scr_intra = nullptr;
 };
 
-// The whole search path for nq queries.  Outputs (any may be null):
-//   scores_host: nq * n_seqs; scores_dev: device pointer (nq * n_seqs);
-//   top_s/top_i: nq * k when k > 0.
-int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off,
-               const sw_scoring *sc, int32_t k, int32_t *top_s, int64_t *top_i,
-               int32_t *scores_host, int32_t *scores_dev, hipStream_t user_stream) {
-    const double t_start = now_ms();
-    if (int rc = validate_scoring(db, sc)) return rc;
-    if (nq < 1) return fail(SW_EINVAL, "nq < 1");
-    if (!q_res || !q_off) return fail(SW_EINVAL, "queries are NULL");
-    if (k < 0 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
-    Batch b;
-    b.nq = nq;
-    for (int32_t q = 0; q < nq; ++q) {
-        const int64_t L = q_off[q + 1] - q_off[q];
-        if (int rc = validate_query(db, q_res + q_off[q], L)) return rc;
-        b.qlen.push_back(L);
-        b.mpad.push_back((int32_t)round_up(L, kQPad));
-        b.qp_off.push_back(b.qp_bytes);
-        b.qp_bytes += (int64_t)db->R * b.mpad.back();
-        b.max_qlen = std::max(b.max_qlen, L);
-        b.sum_qlen += L;
-    }
-    HIPX(hipSetDevice(db->device));
-    hipStream_t st = user_stream ? user_stream : db->stream;
-    const Plan plan = plan_for(db, b.max_qlen);
-    const int R = db->R, A = db->alphabet;
-    const int64_t n = db->n_seqs;
-
-    // ---- work lists (host) ----
-    const int W = plan.waves;
-    const int nblk = (db->n_groups + W - 1) / W;
-    std::vector<std::pair<int64_t, int64_t>> inter_items;   // (cost, q * nblk + blk)
-    inter_items.reserve((size_t)nq * nblk);
-    for (int32_t q = 0; q < nq; ++q) {
-        const int64_t strips = b.mpad[q] / plan.strip;
-        for (int bk = 0; bk < nblk; ++bk) {
-            const int last = std::min(db->n_groups, (bk + 1) * W) - 1;
-            inter_items.push_back({(int64_t)db->grp_rows[last] * strips, (int64_t)q * nblk + bk});
-        }
-    }
-    std::stable_sort(inter_items.begin(), inter_items.end(),
-                     [](const auto &x, const auto &y) { return x.first > y.first; });
-    const int WI = 4;   // waves per workgroup of the wave-per-pair kernel
-    const int64_t nlong = (int64_t)db->long_ids.size();
-    const int64_t nlblk = (nlong + WI - 1) / WI;
-    std::vector<std::pair<int64_t, int64_t>> intra_items;
-    for (int32_t q = 0; q < nq; ++q)
-        for (int64_t bk = 0; bk < nlblk; ++bk)
-            intra_items.push_back({db->len[db->long_ids[bk * WI]] * b.qlen[q], (int64_t)q * nlblk + bk});
-    std::stable_sort(intra_items.begin(), intra_items.end(),
-                     [](const auto &x, const auto &y) { return x.first > y.first; });
-    const int64_t n_inter = (int64_t)inter_items.size(), n_intra = (int64_t)intra_items.size();
-    if (n_inter > INT32_MAX || n_intra > INT32_MAX || (int64_t)nq * n > ((int64_t)1 << 40))
-        return fail(SW_EINVAL, "batch too large");
-
-    // ---- host staging: profiles, query meta, items ----
-    const size_t sz_qp = (size_t)round_up(b.qp_bytes, 256);
-    const size_t sz_meta = (size_t)round_up((size_t)nq * (8 + 4 + 4), 256);
-    const size_t sz_items = (size_t)round_up((n_inter * 2 + n_intra * (1 + WI)) * 4, 256);
-    if (int rc = db->h_stage.reserve(sz_qp + sz_meta + sz_items)) return rc;
-    // The staging buffer may still feed copies of a previous call on another stream.
-    HIPX(hipStreamSynchronize(st));
-    uint8_t *hs = db->h_stage.as<uint8_t>();
-    int8_t *qp = (int8_t *)hs;
-    for (int32_t q = 0; q < nq; ++q) {
-        const uint8_t *qq = q_res + q_off[q];
-        const int mp = b.mpad[q];
-        int8_t *base = qp + b.qp_off[q];
-        for (int r = 0; r < R; ++r) {
-            int8_t *row = base + (int64_t)r * mp;
-            if (r < A)
-                for (int64_t j = 0; j < b.qlen[q]; ++j) row[j] = sc->matrix[qq[j] * A + r];
-            else
-                std::memset(row, 0, (size_t)b.qlen[q]);
-            std::memset(row + b.qlen[q], 0, (size_t)(mp - b.qlen[q]));
-        }
-    }
-    int64_t *m_off = (int64_t *)(hs + sz_qp);
-    int32_t *m_mpad = (int32_t *)(m_off + nq);
-    int32_t *m_qlen = m_mpad + nq;
-    for (int32_t q = 0; q < nq; ++q) {
-        m_off[q] = b.qp_off[q];
-        m_mpad[q] = b.mpad[q];
-        m_qlen[q] = (int32_t)b.qlen[q];
-    }
-    int32_t *it_q = (int32_t *)(hs + sz_qp + sz_meta);
-    int32_t *it_g = it_q + n_inter;
-    int32_t *il_q = it_g + n_inter;
-    int32_t *il_ids = il_q + n_intra;
-    for (int64_t i = 0; i < n_inter; ++i) {
-        const int64_t key = inter_items[i].second;
-        it_q[i] = (int32_t)(key / nblk);
-        it_g[i] = (int32_t)((key % nblk) * W);
-    }
-    for (int64_t i = 0; i < n_intra; ++i) {
-        const int64_t key = intra_items[i].second;
-        il_q[i] = (int32_t)(key / nlblk);
-        const int64_t bk = key % nlblk;
-        for (int w = 0; w < WI; ++w) {
-            const int64_t x = bk * WI + w;
-            il_ids[i * WI + w] = x < nlong ? db->long_ids[x] : -1;
-        }
-    }
-
-    // ---- device workspaces ----
-    if (int rc = db->w_qp.reserve(sz_qp + sz_meta + sz_items)) return rc;
-    if (int rc = db->w_scores.reserve((size_t)nq * n * 4 + 4)) return rc;
-    if (int rc = db->w_counters.reserve(256)) return rc;
-    if (int rc = db->w_ovf.reserve((size_t)nq * n * 8 + 8)) return rc;
-    const int grid_inter = (int)std::min<int64_t>(n_inter, inter_max_grid(R, plan.strip, W));
-    if (n_inter > 0)
-        if (int rc = db->w_scr_inter.reserve((size_t)grid_inter * W * db->max_rows * 512)) return rc;
-    const int Ti = intra_T_for(b.max_qlen);
-    const int intra_lds = intra_lds_bytes(R, Ti);
-    const int intra_per_cu = std::max(1, std::min(160 * 1024 / (intra_lds + 64), 8));
-    const int grid_intra_cap = intra_per_cu * db->cus;
-    const int64_t max_len_pad = round_up(std::max<int64_t>(db->max_len, 1), 64) + 128;
-    const int grid_long = (int)std::min<int64_t>(n_intra, grid_intra_cap);
-    const int grid_ovf = std::min(grid_intra_cap * WI, 4096);
-    const int64_t intra_slots = std::max<int64_t>((int64_t)grid_long * WI, grid_ovf);
-    if (int rc = db->w_scr_intra.reserve((size_t)intra_slots * max_len_pad * 8)) return rc;
-    uint8_t *dq = db->w_qp.as<uint8_t>();
-    HIPX(hipMemcpyAsync(dq, hs, sz_qp + sz_meta + sz_items, hipMemcpyHostToDevice, st));
-    int32_t *ctr = db->w_counters.as<int32_t>();
-    int32_t *scores = scores_dev ? scores_dev : db->w_scores.as<int32_t>();
-    int32_t *ovf_q = db->w_ovf.as<int32_t>();
-    int32_t *ovf_id = ovf_q + (size_t)nq * n;
-
-    QuerySet qs;
-    qs.qp = (const int8_t *)dq;
-    qs.qp_off = (const int64_t *)(dq + sz_qp);
-    qs.mpad = (const int32_t *)(qs.qp_off + nq);
-    qs.qlen = qs.mpad + nq;
-    const int32_t *d_it = (const int32_t *)(dq + sz_qp + sz_meta);
-
-    HIPX(launch_fill_i32(ctr, 0, 64, st));
-    HIPX(hipEventRecord(db->ev[0], st));
-    if (n_inter > 0) {
+// Enqueue one pass: counter reset (a fill kernel, safe under graph capture),
+// lane-per-subject kernel, wave-per-pair kernel on the long list, exact
+// recompute of flagged lanes.  Optional events bracket the first kernel.
+int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_t st,
+                 hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+    HIPX(launch_fill_i32(b.counters, 0, 4, st));
+    if (ev_a) HIPX(hipEventRecord(ev_a, st));
+    if (b.n_inter > 0) {
         InterArgs a{};
         a.codes = db->d_codes.as<uint16_t>();
         a.grp_base = db->d_grp_base.as<int64_t>();
         a.grp_rows = db->d_grp_rows.as<int32_t>();
         a.grp_ids = db->d_grp_ids.as<int32_t>();
         a.n_groups = db->n_groups;
-        a.item_q = d_it;
-        a.item_g = d_it + n_inter;
-        a.n_items = (int32_t)n_inter;
-        a.counter = ctr + 0;
-        a.qs = qs;
-        a.R = R;
-        const int cap = plan.tier == TIER_I16X2 ? 32767 : 2048;
-        a.alpha = std::min(sc->alpha, cap);
-        a.beta = std::min(sc->beta, cap);
-        a.thr = plan.thr;
-        a.scratch = db->w_scr_inter.as<uint32_t>();
+        a.item_q = b.it_q;
+        a.item_g = b.it_g;
+        a.n_items = (int32_t)b.n_inter;
+        a.counter = b.counters + 0;
+        a.qs = b.qs;
+        a.R = db->R;
+        a.thr = L.plan.thr;
+        a.scratch = b.scr_inter;
         a.max_rows = db->max_rows;
-        a.scores = scores;
-        a.n_seqs = n;
-        a.ovf_q = ovf_q;
-        a.ovf_id = ovf_id;
-        a.ovf_count = ctr + 1;
-        a.ovf_cap = (int64_t)nq * n;
-        HIPX(launch_inter(a, plan.tier, plan.strip, W, grid_inter, st));
+        a.scores = b.scores;
+        a.n_seqs = db->n_seqs;
+        a.ovf_q = b.ovf_q;
+        a.ovf_id = b.ovf_id;
+        a.ovf_count = b.counters + 1;
+        a.ovf_cap = b.ovf_cap;
+        HIPX(launch_inter(a, L.plan.tier, L.plan.strip, L.plan.waves, L.grid_inter, st));
     }
-    HIPX(hipEventRecord(db->ev[1], st));
+    if (ev_b) HIPX(hipEventRecord(ev_b, st));
     IntraArgs ia{};
     ia.res = db->d_res.as<uint8_t>();
     ia.off = db->d_off.as<int64_t>();
-    ia.qs = qs;
-    ia.R = R;
-    ia.alpha = sc->alpha;
-    ia.beta = sc->beta;
-    ia.pass_scratch = db->w_scr_intra.as<int32_t>();
-    ia.max_len_pad = max_len_pad;
-    ia.scores = scores;
-    ia.n_seqs = n;
-    if (n_intra > 0) {
+    ia.qs = b.qs;
+    ia.R = db->R;
+    ia.pass_scratch = b.scr_intra;
+    ia.max_len_pad = intra_scratch_rows(db);
+    ia.scores = b.scores;
+    ia.n_seqs = db->n_seqs;
+    if (b.n_intra > 0) {
         IntraArgs la = ia;
-        la.item_q = d_it + 2 * n_inter;
-        la.item_ids = la.item_q + n_intra;
-        la.n_items = (int32_t)n_intra;
-        la.counter = ctr + 2;
-        HIPX(launch_intra(la, Ti, WI, grid_long, st));
+        la.item_q = b.il_q;
+        la.item_ids = b.il_ids;
+        la.n_items = (int32_t)b.n_intra;
+        la.counter = b.counters + 2;
+        HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
     }
-    if (n_inter > 0) {
+    if (b.n_inter > 0) {
         IntraArgs oa = ia;
-        oa.item_q = ovf_q;
-        oa.item_ids = ovf_id;
-        oa.n_items_dev = ctr + 1;
-        oa.counter = ctr + 3;
-        HIPX(launch_intra(oa, 16, 1, grid_ovf, st));
+        oa.item_q = b.ovf_q;
+        oa.item_ids = b.ovf_id;
+        oa.n_items_dev = b.counters + 1;
+        oa.counter = b.counters + 3;
+        HIPX(launch_intra(oa, 16, 1, L.grid_ovf, st));
     }
-    HIPX(hipEventRecord(db->ev[2], st));
+    return SW_OK;
+}
 
+size_t topk_work_bytes(int32_t nq, int32_t k) {
+    return (size_t)nq * (256 * 4 + 4 * 4 + kTopkBlocks * 4 + (size_t)k * 8);
+}
+
+TopkWork topk_work(void *base, int32_t nq, int32_t k) {
+    TopkWork tw;
+    tw.hist = (uint32_t *)base;
+    tw.state = (int32_t *)(tw.hist + (size_t)nq * 256);
+    tw.eqcnt = tw.state + (size_t)nq * 4;
+    tw.cand_s = tw.eqcnt + (size_t)nq * kTopkBlocks;
+    tw.cand_i = tw.cand_s + (size_t)nq * k;
+    return tw;
+}
+
+// Layout of the per-call staging area (host pinned -> device, one copy).
+struct StageLayout {
+    size_t prof = 0, ptrs = 0, mpad = 0, qlen = 0, gap = 0, items = 0, total = 0;
+};
+
+StageLayout stage_layout(int32_t nq, int64_t prof_bytes, const Items &it) {
+    // Fixed-size parts first: their offsets depend only on nq and the item
+    // counts, which a captured graph's key pins; the profiles go last.
+    StageLayout s;
+    size_t o = 0;
+    s.ptrs = o;
+    o += (size_t)round_up((int64_t)nq * 8, 256);
+    s.mpad = o;
+    o += (size_t)round_up((int64_t)nq * 4, 256);
+    s.qlen = o;
+    o += (size_t)round_up((int64_t)nq * 4, 256);
+    s.gap = o;
+    o += (size_t)round_up((int64_t)nq * 8, 256);
+    s.items = o;
+    o += (size_t)round_up((int64_t)(it.inter_q.size() * 2 + it.intra_q.size() * (1 + kIntraWaves)) * 4, 256);
+    s.prof = o;
+    o += (size_t)round_up(prof_bytes, 256);
+    s.total = o;
+    return s;
+}
+
+// The search path for nq queries in one fused pass.  Outputs (any may be null):
+//   scores_host: nq * n_seqs; scores_dev: device pointer (nq * n_seqs);
+//   top_s/top_i: nq * k when k > 0.
+//   item_stride > 1 evaluates only every stride-th block (autotuner timing).
+//   use_graph: capture the device work in a HIP graph and replay it on later
+//   calls of the same shape.
+int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off,
+               const sw_scoring *sc, int32_t k, int32_t *top_s, int64_t *top_i,
+               int32_t *scores_host, int32_t *scores_dev, hipStream_t user_stream,
+               int64_t item_stride = 1, bool use_graph = false) {
+    const double t_start = now_ms();
+    TRY(validate_scoring(db, sc));
+    if (nq < 1) return fail(SW_EINVAL, "nq < 1");
+    if (!q_res || !q_off) return fail(SW_EINVAL, "queries are NULL");
+    if (k < 0 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
+    std::vector<int64_t> qlen(nq);
+    std::vector<int32_t> mpad(nq);
+    std::vector<int64_t> poff(nq);
+    int64_t prof_bytes = 0, sum_qlen = 0, max_qlen = 0;
+    for (int32_t q = 0; q < nq; ++q) {
+        qlen[q] = q_off[q + 1] - q_off[q];
+        TRY(validate_query(db, q_res + q_off[q], qlen[q]));
+        mpad[q] = (int32_t)round_up(qlen[q], kQPad);
+        poff[q] = prof_bytes;
+        prof_bytes += (int64_t)db->R * mpad[q];
+        sum_qlen += qlen[q];
+        max_qlen = std::max(max_qlen, qlen[q]);
+    }
+    if ((int64_t)nq * db->n_seqs > ((int64_t)1 << 40)) return fail(SW_EINVAL, "batch too large");
+    HIPX(hipSetDevice(db->device));
+    hipStream_t st = user_stream ? user_stream : db->stream;
+    const Plan plan = plan_for(db, max_qlen);
+    const int64_t n = db->n_seqs;
+
+    std::vector<int32_t> slots(nq);
+    std::iota(slots.begin(), slots.end(), 0);
+    Items it;
+    const int64_t nblk = (db->n_groups + plan.waves - 1) / plan.waves;
+    build_items(db, plan, slots, mpad, qlen, 0, nblk, true, item_stride, it);
+    const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
+    if (n_inter > INT32_MAX || n_intra > INT32_MAX) return fail(SW_EINVAL, "batch too large");
+    const Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra);
+
+    // ---- device workspaces ----
+    const StageLayout sl = stage_layout(nq, prof_bytes, it);
+    TRY(db->w_stage.reserve(sl.total));
+    TRY(db->w_scores.reserve((size_t)nq * n * 4 + 4));
+    TRY(db->w_counters.reserve(256));
+    TRY(db->w_ovf.reserve((size_t)nq * n * 8 + 8));
+    if (n_inter > 0)
+        TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * db->max_rows * 512));
+    const int64_t intra_slots = std::max<int64_t>((int64_t)L.grid_long * kIntraWaves, L.grid_ovf);
+    TRY(db->w_scr_intra.reserve((size_t)intra_slots * intra_scratch_rows(db) * 8));
     if (k > 0) {
-        const size_t tk = (size_t)nq * (256 * 4 + 4 * 4 + kTopkBlocks * 4 + (size_t)k * 8);
-        if (int rc = db->w_topk.reserve(tk)) return rc;
-        if (int rc = db->w_top.reserve((size_t)nq * k * 12)) return rc;
-        TopkWork tw;
-        tw.hist = db->w_topk.as<uint32_t>();
-        tw.state = (int32_t *)(tw.hist + (size_t)nq * 256);
-        tw.eqcnt = tw.state + (size_t)nq * 4;
-        tw.cand_s = tw.eqcnt + (size_t)nq * kTopkBlocks;
-        tw.cand_i = tw.cand_s + (size_t)nq * k;
-        int64_t *d_ti = db->w_top.as<int64_t>();
-        int32_t *d_ts = (int32_t *)(d_ti + (size_t)nq * k);
-        HIPX(launch_topk(scores, n, nq, k, tw, d_ts, d_ti, st));
+        TRY(db->w_topk.reserve(topk_work_bytes(nq, k)));
+        TRY(db->w_top.reserve((size_t)nq * k * 12));
+    }
+
+    // ---- host staging (the previous call may still be reading it) ----
+    TRY(db->h_stage.reserve(sl.total));
+    HIPX(hipStreamSynchronize(st));
+    uint8_t *hs = db->h_stage.as<uint8_t>();
+    uint8_t *ds = db->w_stage.as<uint8_t>();
+    for (int32_t q = 0; q < nq; ++q)
+        write_profile((int8_t *)(hs + sl.prof + poff[q]), q_res + q_off[q], qlen[q], mpad[q], sc,
+                      db->R);
+    {
+        const int8_t **ptrs = (const int8_t **)(hs + sl.ptrs);
+        int32_t *mp = (int32_t *)(hs + sl.mpad), *ql = (int32_t *)(hs + sl.qlen);
+        int32_t *gp = (int32_t *)(hs + sl.gap);
+        for (int32_t q = 0; q < nq; ++q) {
+            ptrs[q] = (const int8_t *)(ds + sl.prof + poff[q]);
+            mp[q] = mpad[q];
+            ql[q] = (int32_t)qlen[q];
+            gp[2 * q] = sc->alpha;
+            gp[2 * q + 1] = sc->beta;
+        }
+        int32_t *p = (int32_t *)(hs + sl.items);
+        std::memcpy(p, it.inter_q.data(), n_inter * 4);
+        std::memcpy(p + n_inter, it.inter_g.data(), n_inter * 4);
+        std::memcpy(p + 2 * n_inter, it.intra_q.data(), n_intra * 4);
+        std::memcpy(p + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * kIntraWaves * 4);
+    }
+    HIPX(hipMemcpyAsync(ds, hs, sl.total, hipMemcpyHostToDevice, st));
+
+    PassBufs pb;
+    pb.qs.qp = (const int8_t *const *)(ds + sl.ptrs);
+    pb.qs.mpad = (const int32_t *)(ds + sl.mpad);
+    pb.qs.qlen = (const int32_t *)(ds + sl.qlen);
+    pb.qs.gap = (const int32_t *)(ds + sl.gap);
+    pb.it_q = (const int32_t *)(ds + sl.items);
+    pb.it_g = pb.it_q + n_inter;
+    pb.il_q = pb.it_g + n_inter;
+    pb.il_ids = pb.il_q + n_intra;
+    pb.n_inter = n_inter;
+    pb.n_intra = n_intra;
+    pb.scores = scores_dev ? scores_dev : db->w_scores.as<int32_t>();
+    pb.ovf_q = db->w_ovf.as<int32_t>();
+    pb.ovf_id = pb.ovf_q + (size_t)nq * n;
+    pb.ovf_cap = (int64_t)nq * n;
+    pb.counters = db->w_counters.as<int32_t>();
+    pb.scr_inter = db->w_scr_inter.as<uint32_t>();
+    pb.scr_intra = db->w_scr_intra.as<int32_t>();
+    int64_t *d_ti = k > 0 ? db->w_top.as<int64_t>() : nullptr;
+    int32_t *d_ts = d_ti ? (int32_t *)(d_ti + (size_t)nq * k) : nullptr;
+
+    auto enqueue_all = [&](hipStream_t s, bool events) -> int {
+        TRY(enqueue_pass(db, L, pb, s, events ? db->ev[0] : nullptr, events ? db->ev[1] : nullptr));
+        if (events) HIPX(hipEventRecord(db->ev[2], s));
+        if (k > 0)
+            HIPX(launch_topk(pb.scores, n, nq, nullptr, k, topk_work(db->w_topk.p, nq, k), d_ts,
+                             d_ti, s));
+        return SW_OK;
+    };
+
+    bool graphed = false;
+    if (use_graph && db->opts.graph >= 0) {
+        // Every kernel argument of the pass is fixed by this key; what changes
+        // between calls of one shape (profiles, items) arrives by the staging copy.
+        char key[512];
+        snprintf(key, sizeof key, "%d|%d|%d|%d|%d|%d|%lld|%lld|%d|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%p",
+                 nq, k, plan.tier, plan.strip, plan.waves, plan.thr, (long long)n_inter,
+                 (long long)n_intra, L.Ti, L.grid_inter, L.grid_long, L.grid_ovf, (void *)ds,
+                 (void *)pb.scores, (void *)pb.ovf_q, (void *)pb.counters, (void *)pb.scr_inter,
+                 (void *)pb.scr_intra, db->w_topk.p, (void *)d_ti);
+        if (!db->graph || db->graph_key != key) {
+            if (db->graph) {
+                (void)hipGraphExecDestroy(db->graph);
+                db->graph = nullptr;
+            }
+            // Capture on the library's own stream, ordered after the staging copy.
+            hipStream_t cs = db->stream;
+            if (st != cs) {
+                HIPX(hipEventRecord(db->ev[3], st));
+                HIPX(hipStreamWaitEvent(cs, db->ev[3], 0));
+            }
+            HIPX(hipStreamSynchronize(cs));
+            hipGraph_t g = nullptr;
+            HIPX(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            int rc = enqueue_all(cs, false);
+            hipError_t e = hipStreamEndCapture(cs, &g);
+            if (rc != SW_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return rc;
+            }
+            if (e != hipSuccess) return fail(SW_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&db->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                db->graph = nullptr;
+                return fail(SW_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+            }
+            db->graph_key = key;
+        }
+        HIPX(hipEventRecord(db->ev[0], st));
+        HIPX(hipGraphLaunch(db->graph, st));
+        HIPX(hipEventRecord(db->ev[2], st));
+        graphed = true;
+    } else {
+        TRY(enqueue_all(st, true));
+    }
+    if (k > 0) {
         HIPX(hipMemcpyAsync(top_s, d_ts, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
         HIPX(hipMemcpyAsync(top_i, d_ti, (size_t)nq * k * 8, hipMemcpyDeviceToHost, st));
     }
-    HIPX(hipEventRecord(db->ev[3], st));
     if (scores_host && n > 0)
-        HIPX(hipMemcpyAsync(scores_host, scores, (size_t)nq * n * 4, hipMemcpyDeviceToHost, st));
+        HIPX(hipMemcpyAsync(scores_host, pb.scores, (size_t)nq * n * 4, hipMemcpyDeviceToHost, st));
     int32_t ctr_h[4] = {0, 0, 0, 0};
-    HIPX(hipMemcpyAsync(ctr_h, ctr, 16, hipMemcpyDeviceToHost, st));
-    if (!(scores_dev && user_stream)) HIPX(hipStreamSynchronize(st));
-    else HIPX(hipStreamSynchronize(st));
+    HIPX(hipMemcpyAsync(ctr_h, pb.counters, 16, hipMemcpyDeviceToHost, st));
+    HIPX(hipStreamSynchronize(st));
 
-    float ms_k = 0, ms_i = 0;
+    float ms_k = 0, ms_i = -1;
     HIPX(hipEventElapsedTime(&ms_k, db->ev[0], db->ev[2]));
-    HIPX(hipEventElapsedTime(&ms_i, db->ev[0], db->ev[1]));
+    if (!graphed) HIPX(hipEventElapsedTime(&ms_i, db->ev[0], db->ev[1]));
     sw_stats &s = db->last;
     s = sw_stats{};
-    s.cells = b.sum_qlen * db->total_res;
+    s.cells = sum_qlen * db->total_res;
     int64_t padded = 0;
     for (int32_t q = 0; q < nq; ++q)
-        padded += (int64_t)b.mpad[q] * db->inter_padded_rows +
-                  round_up(b.qlen[q], 64LL * Ti) * db->long_res;
+        padded += (int64_t)mpad[q] * db->inter_padded_rows +
+                  round_up(qlen[q], 64LL * L.Ti) * db->long_res;
     s.padded_cells = padded;
-    s.inter_cells = b.sum_qlen * db->inter_res;
+    s.inter_cells = sum_qlen * db->inter_res;
     s.recomputed_pairs = ctr_h[1];
-    s.intra_pairs = (int64_t)nlong * nq;
+    s.intra_pairs = (int64_t)db->long_ids.size() * nq;
     s.kernel_ms = ms_k;
     s.inter_ms = ms_i;
     s.total_ms = now_ms() - t_start;
     s.tier = plan.tier;
     s.strip = plan.strip;
     s.waves = plan.waves;
+    s.graphed = graphed ? 1 : 0;
     return SW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: time candidate plans on a strided sample of the work, per
+// query-length bucket, and keep the fastest.
+// ---------------------------------------------------------------------------
+const Plan kCandidates[] = {
+    {TIER_F16X2, 32, 4, 0}, {TIER_F16X2, 64, 4, 0}, {TIER_F16X2, 32, 8, 0},
+    {TIER_F16X2, 16, 8, 0}, {TIER_F16X2, 16, 4, 0}, {TIER_I16X2, 32, 4, 0},
+    {TIER_I16X2, 64, 4, 0}, {TIER_I16X2, 32, 8, 0},
+};
+
+bool read_cache(sw_db *db, const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    std::string text;
+    char buf[4096];
+    size_t r;
+    while ((r = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, r);
+    fclose(f);
+    const std::string sig = "\"signature\": \"" + db->signature + "\"";
+    if (text.find(sig) == std::string::npos) return false;
+    std::map<int, Plan> t;
+    size_t pos = 0;
+    while ((pos = text.find("{\"bucket\":", pos)) != std::string::npos) {
+        int b, tier, strip, waves;
+        if (sscanf(text.c_str() + pos, "{\"bucket\": %d, \"tier\": %d, \"strip\": %d, \"waves\": %d",
+                   &b, &tier, &strip, &waves) == 4 &&
+            (tier == TIER_F16X2 || tier == TIER_I16X2) && (strip == 16 || strip == 32 || strip == 64) &&
+            (waves == 4 || waves == 6 || waves == 8)) {
+            Plan p;
+            p.tier = tier;
+            p.strip = strip;
+            p.waves = waves;
+            t[b] = p;
+        }
+        ++pos;
+    }
+    if (t.empty()) return false;
+    db->tuned = t;
+    return true;
+}
+
+int write_cache(const sw_db *db, const char *path, const std::map<int, double> &gcups) {
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(SW_EINVAL, "cannot write autotune cache %s", path);
+    fprintf(f, "{\"signature\": \"%s\", \"entries\": [\n", db->signature.c_str());
+    size_t i = 0;
+    for (const auto &kv : db->tuned) {
+        auto g = gcups.find(kv.first);
+        fprintf(f, "  {\"bucket\": %d, \"tier\": %d, \"strip\": %d, \"waves\": %d, \"gcups\": %.1f}%s\n",
+                kv.first, kv.second.tier, kv.second.strip, kv.second.waves,
+                g == gcups.end() ? 0.0 : g->second, ++i < db->tuned.size() ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    fclose(f);
+    return SW_OK;
+}
+
+int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,
+             const char *cache_path) {
+    TRY(validate_scoring(db, sc));
+    if (n_qlens < 0 || (n_qlens > 0 && !qlens)) return fail(SW_EINVAL, "bad query-length list");
+    if (cache_path && read_cache(db, cache_path)) return SW_OK;
+    if (db->n_groups == 0) return SW_OK;   // nothing runs lane-per-subject
+    const sw_search_opts saved = db->opts;
+    std::map<int, double> best_gcups;
+    // every stride-th block only, so a candidate costs a fraction of a search
+    const int64_t stride = std::max<int64_t>(1, std::min<int64_t>(8, db->n_groups / 2048));
+    uint32_t lcg = 12345u;
+    for (int32_t x = 0; x < n_qlens; ++x) {
+        const int64_t L = std::max(1, std::min(qlens[x], SW_MAX_LEN));
+        const int b = qlen_bucket(L);
+        if (best_gcups.count(b)) continue;
+        std::vector<uint8_t> q((size_t)L);
+        for (auto &c : q) {
+            lcg = lcg * 1664525u + 1013904223u;
+            c = (uint8_t)((lcg >> 16) % (uint32_t)db->alphabet);
+        }
+        const int64_t off[2] = {0, L};
+        double best = -1;
+        Plan best_plan;
+        for (const Plan &cand : kCandidates) {
+            if (inter_lds_bytes(db->R, cand.strip) > 150 * 1024) continue;
+            sw_search_opts o{};
+            o.tier = cand.tier;
+            o.strip = cand.strip;
+            o.waves = cand.waves;
+            db->opts = o;
+            double ms = 1e30;
+            for (int rep = 0; rep < 2; ++rep) {
+                int rc = run_search(db, 1, q.data(), off, sc, 0, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr, stride);
+                if (rc != SW_OK) {
+                    db->opts = saved;
+                    return rc;
+                }
+                ms = std::min(ms, db->last.inter_ms);
+            }
+            const double gc = (double)L * db->inter_res / stride / (ms * 1e6);
+            if (gc > best) {
+                best = gc;
+                best_plan = cand;
+            }
+        }
+        db->tuned[b] = best_plan;
+        best_gcups[b] = best;
+    }
+    db->opts = saved;
+    if (cache_path) TRY(write_cache(db, cache_path, best_gcups));
+    return SW_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// Serving: continuous batching over database chunks.
+//
+// The database stays resident.  Its lane-per-subject blocks are cut into
+// chunks; the long list is one more position of a circular scan.  Each pass
+// runs every admitted request against the scan's current position in one
+// launch; a request admitted between passes starts at the next position and
+// completes once it has visited every position.  A request's scores do not
+// depend on which others share its passes, so results are the same alone and
+// in the mix.
+// ===========================================================================
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    std::vector<uint8_t> query;
+    std::vector<int8_t> matrix;
+    int32_t alpha = 0, beta = 0, k = 0;
+    int64_t bytes = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int32_t slot = -1;
+    int32_t remaining = 0;   // database positions still to visit
+    int32_t passes = 0;
+    int rc = SW_OK;
+    bool done = false;
+    std::vector<int32_t> top_s;
+    std::vector<int64_t> top_i;
+};
+
+}  // namespace
+
+struct sw_server {
+    sw_db *db = nullptr;
+    sw_server_opts opts{};
+    Plan plan;
+    int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
+    bool has_long = false;
+    int32_t slots = 0;
+    // device state
+    std::vector<std::unique_ptr<DevBuf>> prof;   // query profile per slot
+    DevBuf d_meta, d_scores, d_ovf, d_counters, d_scr_inter, d_scr_intra, d_items, d_topk, d_top,
+        d_rows;
+    HostBuf h_items, h_meta, h_top, h_rows;
+    Launch L;
+    // host state
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::shared_ptr<Request>> waiting;
+    std::vector<std::shared_ptr<Request>> active;   // by slot (nullptr = free)
+    std::unordered_map<uint64_t, std::shared_ptr<Request>> table;
+    uint64_t next_ticket = 1;
+    int64_t used_bytes = 0;
+    int32_t waiters = 0;     // threads inside sw_server_wait
+    bool stop = false;
+    int64_t position = 0;
+    std::thread worker;
+    std::string fatal;
+};
+
+namespace {
+
+int server_setup(sw_server *s) {
+    sw_db *db = s->db;
+    HIPX(hipSetDevice(db->device));
+    s->plan = plan_for(db, 512);
+    const int W = s->plan.waves;
+    s->blocks = (db->n_groups + W - 1) / W;
+    const int64_t cb = s->opts.chunk_groups > 0 ? (s->opts.chunk_groups + W - 1) / W
+                                                : std::max<int64_t>(1, (s->blocks + 15) / 16);
+    s->chunk_blocks = std::max<int64_t>(1, cb);
+    s->n_chunks = s->blocks > 0 ? (s->blocks + s->chunk_blocks - 1) / s->chunk_blocks : 0;
+    s->has_long = !db->long_ids.empty();
+    s->n_pos = s->n_chunks + (s->has_long ? 1 : 0);
+    s->slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
+    if (s->opts.memory_budget <= 0) s->opts.memory_budget = (int64_t)1 << 30;
+    if (s->opts.queue_capacity <= 0) s->opts.queue_capacity = 65536;
+    s->prof.resize(s->slots);
+    for (auto &p : s->prof) p.reset(new DevBuf());
+    s->active.assign(s->slots, nullptr);
+    const int64_t n = db->n_seqs;
+    // the largest pass: every slot against one chunk, or against the long list
+    const int64_t inter_items = (int64_t)s->slots * s->chunk_blocks;
+    const int64_t nlblk = ((int64_t)db->long_ids.size() + kIntraWaves - 1) / kIntraWaves;
+    const int64_t intra_items = (int64_t)s->slots * nlblk;
+    s->L = launch_config(db, s->plan, 1 << 14, std::max<int64_t>(inter_items, 1),
+                         std::max<int64_t>(intra_items, 1));
+    TRY(s->d_meta.reserve((size_t)s->slots * 24 + 256));
+    TRY(s->h_meta.reserve((size_t)s->slots * 24 + 256));
+    std::memset(s->h_meta.p, 0, (size_t)s->slots * 24 + 256);
+    TRY(s->d_scores.reserve((size_t)s->slots * n * 4 + 4));
+    const int64_t chunk_subj = s->chunk_blocks * W * kGroup;
+    TRY(s->d_ovf.reserve((size_t)s->slots * chunk_subj * 8 + 8));
+    TRY(s->d_counters.reserve(256));
+    if (db->n_groups > 0)
+        TRY(s->d_scr_inter.reserve((size_t)s->L.grid_inter * W * db->max_rows * 512));
+    const int64_t islots = std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, s->L.grid_ovf);
+    TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
+    const size_t items_bytes =
+        (size_t)(std::max(inter_items * 2, intra_items * (1 + kIntraWaves)) + 64) * 4;
+    TRY(s->d_items.reserve(items_bytes));
+    TRY(s->h_items.reserve(items_bytes));
+    TRY(s->d_topk.reserve(topk_work_bytes(s->slots, SW_MAX_K)));
+    TRY(s->d_top.reserve((size_t)s->slots * SW_MAX_K * 12));
+    TRY(s->h_top.reserve((size_t)s->slots * SW_MAX_K * 12));
+    TRY(s->d_rows.reserve((size_t)s->slots * 4));
+    TRY(s->h_rows.reserve((size_t)s->slots * 4));
+    return SW_OK;
+}
+
+// Admit waiting requests in arrival order while a slot and the memory budget
+// allow.  Called with s->mu held; returns the newly admitted requests.
+std::vector<std::shared_ptr<Request>> admit(sw_server *s) {
+    std::vector<std::shared_ptr<Request>> out;
+    while (!s->waiting.empty()) {
+        auto &r = s->waiting.front();
+        int slot = -1;
+        for (int i = 0; i < s->slots; ++i)
+            if (!s->active[i]) {
+                slot = i;
+                break;
+            }
+        if (slot < 0 || s->used_bytes + r->bytes > s->opts.memory_budget) break;
+        r->slot = slot;
+        r->remaining = (int32_t)s->n_pos;
+        r->t_admit = now_ms();
+        s->used_bytes += r->bytes;
+        s->active[slot] = r;
+        out.push_back(r);
+        s->waiting.pop_front();
+    }
+    return out;
+}
+
+int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh,
+                std::vector<std::shared_ptr<Request>> &finished) {
+    sw_db *db = s->db;
+    hipStream_t st = db->stream;
+    const int R = db->R;
+    HIPX(hipStreamSynchronize(st));
+    // profiles and per-slot metadata of newly admitted requests
+    if (!fresh.empty()) {
+        const int8_t **ptrs = (const int8_t **)s->h_meta.p;
+        int32_t *mp = (int32_t *)(s->h_meta.as<uint8_t>() + (size_t)s->slots * 8);
+        int32_t *ql = mp + s->slots;
+        int32_t *gp = ql + s->slots;
+        std::vector<uint8_t> staging;
+        for (auto &r : fresh) {
+            const int64_t L = (int64_t)r->query.size();
+            const int32_t m = (int32_t)round_up(L, kQPad);
+            DevBuf &pb = *s->prof[r->slot];
+            TRY(pb.reserve((size_t)R * m));
+            staging.resize((size_t)R * m);
+            sw_scoring sc{db->alphabet, r->matrix.data(), r->alpha, r->beta};
+            write_profile((int8_t *)staging.data(), r->query.data(), L, m, &sc, R);
+            HIPX(hipMemcpy(pb.p, staging.data(), staging.size(), hipMemcpyHostToDevice));
+            ptrs[r->slot] = pb.as<int8_t>();
+            mp[r->slot] = m;
+            ql[r->slot] = (int32_t)L;
+            gp[2 * r->slot] = r->alpha;
+            gp[2 * r->slot + 1] = r->beta;
+        }
+        HIPX(hipMemcpy(s->d_meta.p, s->h_meta.p, (size_t)s->slots * 24, hipMemcpyHostToDevice));
+    }
+    std::vector<int32_t> slots, mpad;
+    std::vector<int64_t> qlen;
+    for (int i = 0; i < s->slots; ++i)
+        if (s->active[i]) {
+            slots.push_back(i);
+            qlen.push_back((int64_t)s->active[i]->query.size());
+            mpad.push_back((int32_t)round_up(qlen.back(), kQPad));
+        }
+    if (slots.empty()) return SW_OK;
+    const bool long_pos = s->has_long && s->position == s->n_chunks;
+    Items it;
+    if (long_pos) {
+        build_items(db, s->plan, slots, mpad, qlen, 0, 0, true, 1, it);
+    } else {
+        const int64_t b0 = s->position * s->chunk_blocks;
+        const int64_t b1 = std::min(s->blocks, b0 + s->chunk_blocks);
+        build_items(db, s->plan, slots, mpad, qlen, b0, b1, false, 1, it);
+    }
+    const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
+    int32_t *hi = s->h_items.as<int32_t>();
+    std::memcpy(hi, it.inter_q.data(), n_inter * 4);
+    std::memcpy(hi + n_inter, it.inter_g.data(), n_inter * 4);
+    std::memcpy(hi + 2 * n_inter, it.intra_q.data(), n_intra * 4);
+    std::memcpy(hi + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * kIntraWaves * 4);
+    const size_t ib = (size_t)(2 * n_inter + n_intra * (1 + kIntraWaves)) * 4;
+    if (ib) HIPX(hipMemcpyAsync(s->d_items.p, hi, ib, hipMemcpyHostToDevice, st));
+    PassBufs pb;
+    uint8_t *dm = s->d_meta.as<uint8_t>();
+    pb.qs.qp = (const int8_t *const *)dm;
+    pb.qs.mpad = (const int32_t *)(dm + (size_t)s->slots * 8);
+    pb.qs.qlen = pb.qs.mpad + s->slots;
+    pb.qs.gap = pb.qs.qlen + s->slots;
+    pb.it_q = s->d_items.as<int32_t>();
+    pb.it_g = pb.it_q + n_inter;
+    pb.il_q = pb.it_g + n_inter;
+    pb.il_ids = pb.il_q + n_intra;
+    pb.n_inter = n_inter;
+    pb.n_intra = n_intra;
+    pb.scores = s->d_scores.as<int32_t>();
+    const int64_t cap = (int64_t)s->slots * s->chunk_blocks * s->plan.waves * kGroup;
+    pb.ovf_q = s->d_ovf.as<int32_t>();
+    pb.ovf_id = pb.ovf_q + cap;
+    pb.ovf_cap = cap;
+    pb.counters = s->d_counters.as<int32_t>();
+    pb.scr_inter = s->d_scr_inter.as<uint32_t>();
+    pb.scr_intra = s->d_scr_intra.as<int32_t>();
+    Launch L = s->L;
+    L.grid_inter = (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
+    L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
+    TRY(enqueue_pass(db, L, pb, st));
+    // advance every active request; those that visited every position get top-k
+    std::vector<int32_t> done_rows;
+    for (int32_t sl : slots) {
+        auto &r = s->active[sl];
+        r->passes++;
+        if (--r->remaining == 0) {
+            finished.push_back(r);
+            done_rows.push_back(sl);
+        }
+    }
+    if (!done_rows.empty()) {
+        const int32_t nd = (int32_t)done_rows.size();
+        int32_t kmax = 0;
+        for (auto &r : finished) kmax = std::max(kmax, r->k);
+        int32_t *rows_h = s->h_rows.as<int32_t>();
+        std::memcpy(rows_h, done_rows.data(), (size_t)nd * 4);
+        HIPX(hipMemcpyAsync(s->d_rows.p, rows_h, (size_t)nd * 4, hipMemcpyHostToDevice, st));
+        int64_t *d_ti = s->d_top.as<int64_t>();
+        int32_t *d_ts = (int32_t *)(d_ti + (size_t)nd * kmax);
+        HIPX(launch_topk(pb.scores, db->n_seqs, nd, s->d_rows.as<int32_t>(), kmax,
+                         topk_work(s->d_topk.p, nd, kmax), d_ts, d_ti, st));
+        int64_t *h_ti = s->h_top.as<int64_t>();
+        int32_t *h_ts = (int32_t *)(h_ti + (size_t)nd * kmax);
+        HIPX(hipMemcpyAsync(h_ti, d_ti, (size_t)nd * kmax * 12, hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+        for (int32_t x = 0; x < nd; ++x) {
+            auto &r = finished[x];
+            r->top_s.assign(h_ts + (size_t)x * kmax, h_ts + (size_t)x * kmax + r->k);
+            r->top_i.assign(h_ti + (size_t)x * kmax, h_ti + (size_t)x * kmax + r->k);
+        }
+    } else {
+        HIPX(hipStreamSynchronize(st));
+    }
+    return SW_OK;
+}
+
+void server_loop(sw_server *s) {
+    (void)hipSetDevice(s->db->device);
+    for (;;) {
+        std::vector<std::shared_ptr<Request>> fresh;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            auto any_active = [&] {
+                for (auto &a : s->active)
+                    if (a) return true;
+                return false;
+            };
+            s->cv_work.wait(lk, [&] { return s->stop || any_active() || !s->waiting.empty(); });
+            if (s->stop) break;
+            fresh = admit(s);
+        }
+        std::vector<std::shared_ptr<Request>> finished;
+        const int rc = s->n_pos > 0 ? server_pass(s, fresh, finished) : SW_OK;
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (rc != SW_OK) {
+            // a device failure ends every request in flight
+            s->fatal = g_err;
+            for (auto &a : s->active)
+                if (a) {
+                    a->rc = rc;
+                    a->done = true;
+                    a->t_done = now_ms();
+                    s->used_bytes -= a->bytes;
+                    a = nullptr;
+                }
+            s->cv_done.notify_all();
+            continue;
+        }
+        if (s->n_pos == 0) {   // empty database: every admitted request is done at once
+            for (auto &a : s->active)
+                if (a) {
+                    a->top_s.assign(a->k, -1);
+                    a->top_i.assign(a->k, -1);
+                    finished.push_back(a);
+                }
+        }
+        for (auto &r : finished) {
+            r->done = true;
+            r->t_done = now_ms();
+            s->used_bytes -= r->bytes;
+            s->active[r->slot] = nullptr;
+        }
+        if (s->n_pos > 0) s->position = (s->position + 1) % s->n_pos;
+        if (!finished.empty()) s->cv_done.notify_all();
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto &a : s->active)
+        if (a && !a->done) {
+            a->rc = SW_ESTOPPED;
+            a->done = true;
+        }
+    for (auto &w : s->waiting) {
+        w->rc = SW_ESTOPPED;
+        w->done = true;
+    }
+    s->waiting.clear();
+    s->cv_done.notify_all();
 }
 
 }  // namespace
@@ -467,7 +1065,7 @@ extern "C" {
 
 const char *sw_last_error(void) { return g_err.c_str(); }
 
-const char *sw_version(void) { return "swmi 0.1 (gfx950)"; }
+const char *sw_version(void) { return "swmi 0.2 (gfx950)"; }
 
 int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, int32_t alphabet,
                const sw_db_opts *opts, sw_db **out) {
@@ -497,7 +1095,10 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
             th.emplace_back([&, t] {
                 const int64_t lo = total * t / nth, hi = total * (t + 1) / nth;
                 for (int64_t i = lo; i < hi; ++i)
-                    if (residues[i] >= alphabet) { bad[t] = i; return; }
+                    if (residues[i] >= alphabet) {
+                        bad[t] = i;
+                        return;
+                    }
             });
         for (auto &x : th) x.join();
         for (int t = 0; t < nth; ++t)
@@ -526,7 +1127,13 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
         hipDeviceProp_t p;
         HIPX(hipGetDeviceProperties(&p, db->device));
         db->cus = p.multiProcessorCount;
+        char sig[512];
+        snprintf(sig, sizeof sig, "%s|cu%d|n%lld|res%lld|A%d|max%lld", p.gcnArchName,
+                 p.multiProcessorCount, (long long)n_seqs, (long long)total, alphabet,
+                 (long long)max_len);
+        db->signature = sig;
     }
+    HIPX(prepare_kernels());
     HIPX(hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking));
     for (auto &e : db->ev) HIPX(hipEventCreate(&e));
 
@@ -548,8 +1155,8 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
         // Too few subjects to give every SIMD a wavefront: all wave-per-pair.
         if (n_seqs < simds * kGroup) cut = -1;
         else {
-            // Longest lane-per-subject group may hold its SIMD for at most half the
-            // average per-SIMD share of rows.
+            // The longest lane-per-subject group may hold its SIMD for at most half
+            // the average per-SIMD share of rows.
             const double share = (double)total / kGroup / simds;
             cut = std::max<int64_t>(1024, (int64_t)(0.5 * share));
         }
@@ -615,15 +1222,15 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
     }
 
     // ---- upload ----
-    if (int rc = db->d_res.reserve((size_t)std::max<int64_t>(total, 1))) return rc;
-    if (int rc = db->d_off.reserve((size_t)(n_seqs + 1) * 8)) return rc;
+    TRY(db->d_res.reserve((size_t)std::max<int64_t>(total, 1)));
+    TRY(db->d_off.reserve((size_t)(n_seqs + 1) * 8));
     if (total > 0) HIPX(hipMemcpy(db->d_res.p, residues, (size_t)total, hipMemcpyHostToDevice));
     HIPX(hipMemcpy(db->d_off.p, offsets, (size_t)(n_seqs + 1) * 8, hipMemcpyHostToDevice));
     if (ng > 0) {
-        if (int rc = db->d_codes.reserve(codes.size() * 2)) return rc;
-        if (int rc = db->d_grp_base.reserve((size_t)ng * 8)) return rc;
-        if (int rc = db->d_grp_rows.reserve((size_t)ng * 4)) return rc;
-        if (int rc = db->d_grp_ids.reserve(gids.size() * 4)) return rc;
+        TRY(db->d_codes.reserve(codes.size() * 2));
+        TRY(db->d_grp_base.reserve((size_t)ng * 8));
+        TRY(db->d_grp_rows.reserve((size_t)ng * 4));
+        TRY(db->d_grp_ids.reserve(gids.size() * 4));
         HIPX(hipMemcpy(db->d_codes.p, codes.data(), codes.size() * 2, hipMemcpyHostToDevice));
         HIPX(hipMemcpy(db->d_grp_base.p, gbase.data(), (size_t)ng * 8, hipMemcpyHostToDevice));
         HIPX(hipMemcpy(db->d_grp_rows.p, db->grp_rows.data(), (size_t)ng * 4, hipMemcpyHostToDevice));
@@ -637,6 +1244,7 @@ void sw_db_close(sw_db *db) {
     if (!db) return;
     (void)hipSetDevice(db->device);
     if (db->stream) (void)hipStreamSynchronize(db->stream);
+    if (db->graph) (void)hipGraphExecDestroy(db->graph);
     for (auto &e : db->ev)
         if (e) (void)hipEventDestroy(e);
     if (db->stream) (void)hipStreamDestroy(db->stream);
@@ -646,6 +1254,7 @@ void sw_db_close(sw_db *db) {
 int64_t sw_db_size(const sw_db *db) { return db ? db->n_seqs : -1; }
 
 int sw_db_set_opts(sw_db *db, const sw_search_opts *opts) {
+    g_err.clear();
     if (!db) return fail(SW_EINVAL, "db is NULL");
     std::lock_guard<std::mutex> lk(db->mu);
     if (!opts) {
@@ -662,15 +1271,21 @@ int sw_db_set_opts(sw_db *db, const sw_search_opts *opts) {
     if (opts->waves == 6 && opts->strip && opts->strip != 32)
         return fail(SW_EINVAL, "6 waves per workgroup runs with strip 32");
     if (opts->sat_threshold < 0) return fail(SW_EINVAL, "sat_threshold < 0");
+    if (opts->graph < -1 || opts->graph > 0) return fail(SW_EINVAL, "graph must be 0 or -1");
     db->opts = *opts;
     return SW_OK;
 }
 
 int sw_db_last_stats(sw_db *db, sw_stats *out) {
+    g_err.clear();
     if (!db || !out) return fail(SW_EINVAL, "NULL argument");
     std::lock_guard<std::mutex> lk(db->mu);
     *out = db->last;
     return SW_OK;
+}
+
+static int busy(sw_db *db) {
+    return db->server_attached ? fail(SW_EBUSY, "a server is running on this database") : SW_OK;
 }
 
 int sw_db_search(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
@@ -679,6 +1294,7 @@ int sw_db_search(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring
     if (!db) return fail(SW_EINVAL, "db is NULL");
     if (!scores && db->n_seqs > 0) return fail(SW_EINVAL, "scores is NULL");
     std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
     const int64_t off[2] = {0, qlen};
     return run_search(db, 1, query, off, sc, 0, nullptr, nullptr, scores, nullptr,
                       (hipStream_t)hip_stream);
@@ -690,6 +1306,7 @@ int sw_db_search_dev(sw_db *db, const uint8_t *query, int32_t qlen, const sw_sco
     if (!db) return fail(SW_EINVAL, "db is NULL");
     if (!scores_dev && db->n_seqs > 0) return fail(SW_EINVAL, "scores_dev is NULL");
     std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
     const int64_t off[2] = {0, qlen};
     return run_search(db, 1, query, off, sc, 0, nullptr, nullptr, nullptr, scores_dev,
                       (hipStream_t)hip_stream);
@@ -702,6 +1319,7 @@ int sw_db_topk(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *
     if (k < 1 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
     if (!top_scores || !top_idx) return fail(SW_EINVAL, "top-k outputs are NULL");
     std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
     const int64_t off[2] = {0, qlen};
     return run_search(db, 1, query, off, sc, k, top_scores, top_idx, nullptr, nullptr,
                       (hipStream_t)hip_stream);
@@ -715,36 +1333,120 @@ int sw_db_search_batch(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_
     if (k < 1 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
     if (!top_scores || !top_idx) return fail(SW_EINVAL, "top-k outputs are NULL");
     std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
     return run_search(db, nq, q_res, q_off, sc, k, top_scores, top_idx, all_scores, nullptr,
-                      (hipStream_t)hip_stream);
+                      (hipStream_t)hip_stream, 1, true);
 }
 
 int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,
                    const char *cache_path) {
-    (void)sc;
-    (void)qlens;
-    (void)n_qlens;
-    (void)cache_path;
+    g_err.clear();
     if (!db) return fail(SW_EINVAL, "db is NULL");
-    return SW_OK;
+    std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
+    return autotune(db, sc, qlens, n_qlens, cache_path);
 }
 
 int sw_server_start(sw_db *db, const sw_server_opts *opts, sw_server **out) {
-    (void)db;
-    (void)opts;
-    (void)out;
-    return fail(SW_EINVAL, "server not available");
+    g_err.clear();
+    if (!db || !out) return fail(SW_EINVAL, "NULL argument");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
+    if (opts && (opts->max_active < 0 || opts->queue_capacity < 0 || opts->chunk_groups < 0 ||
+                 opts->memory_budget < 0))
+        return fail(SW_EINVAL, "negative server option");
+    std::unique_ptr<sw_server> s(new sw_server());
+    s->db = db;
+    if (opts) s->opts = *opts;
+    TRY(server_setup(s.get()));
+    db->server_attached = true;
+    s->worker = std::thread(server_loop, s.get());
+    *out = s.release();
+    return SW_OK;
 }
+
 int sw_server_submit(sw_server *srv, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
                      int32_t k, uint64_t *ticket) {
-    (void)srv; (void)query; (void)qlen; (void)sc; (void)k; (void)ticket;
-    return fail(SW_EINVAL, "server not available");
+    g_err.clear();
+    if (!srv || !ticket) return fail(SW_EINVAL, "NULL argument");
+    TRY(validate_scoring(srv->db, sc));
+    TRY(validate_query(srv->db, query, qlen));
+    if (k < 1 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
+    auto r = std::make_shared<Request>();
+    r->query.assign(query, query + qlen);
+    r->matrix.assign(sc->matrix, sc->matrix + (size_t)sc->alphabet * sc->alphabet);
+    r->alpha = sc->alpha;
+    r->beta = sc->beta;
+    r->k = k;
+    r->bytes = (int64_t)srv->db->R * round_up(qlen, kQPad) + srv->db->n_seqs * 4 + (int64_t)k * 12;
+    r->t_submit = now_ms();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) return fail(SW_ESTOPPED, "server stopped");
+    if (r->bytes > srv->opts.memory_budget)
+        return fail(SW_EINVAL, "request needs %lld bytes, more than the memory budget",
+                    (long long)r->bytes);
+    if ((int64_t)srv->waiting.size() >= srv->opts.queue_capacity)
+        return fail(SW_EBUSY, "request queue full");
+    r->ticket = srv->next_ticket++;
+    srv->table[r->ticket] = r;
+    srv->waiting.push_back(r);
+    *ticket = r->ticket;
+    srv->cv_work.notify_one();
+    return SW_OK;
 }
+
 int sw_server_wait(sw_server *srv, uint64_t ticket, int32_t *top_scores, int64_t *top_idx,
                    sw_req_stats *stats) {
-    (void)srv; (void)ticket; (void)top_scores; (void)top_idx; (void)stats;
-    return fail(SW_EINVAL, "server not available");
+    g_err.clear();
+    if (!srv || !top_scores || !top_idx) return fail(SW_EINVAL, "NULL argument");
+    std::shared_ptr<Request> r;
+    {
+        std::unique_lock<std::mutex> lk(srv->mu);
+        auto it = srv->table.find(ticket);
+        if (it == srv->table.end())
+            return fail(SW_ENOTFOUND, "unknown ticket %llu", (unsigned long long)ticket);
+        r = it->second;
+        srv->waiters++;
+        srv->cv_done.wait(lk, [&] { return r->done; });
+        srv->table.erase(ticket);
+        srv->waiters--;
+        srv->cv_done.notify_all();
+    }
+    if (r->rc != SW_OK)
+        return fail(r->rc, r->rc == SW_ESTOPPED ? "server stopped" : "device failure: %s",
+                    srv->fatal.c_str());
+    std::memcpy(top_scores, r->top_s.data(), (size_t)r->k * 4);
+    std::memcpy(top_idx, r->top_i.data(), (size_t)r->k * 8);
+    if (stats) {
+        *stats = sw_req_stats{};
+        stats->queue_ms = r->t_admit - r->t_submit;
+        stats->total_ms = r->t_done - r->t_submit;
+        stats->cells = (int64_t)r->query.size() * srv->db->total_res;
+        stats->passes = r->passes;
+    }
+    return SW_OK;
 }
-void sw_server_stop(sw_server *srv) { (void)srv; }
+
+void sw_server_stop(sw_server *srv) {
+    if (!srv) return;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_all();
+    if (srv->worker.joinable()) srv->worker.join();
+    {
+        // threads blocked in sw_server_wait have been woken with SW_ESTOPPED;
+        // let them leave before the server goes away
+        std::unique_lock<std::mutex> lk(srv->mu);
+        srv->cv_done.wait(lk, [&] { return srv->waiters == 0; });
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->db->mu);
+        srv->db->server_attached = false;
+    }
+    delete srv;
+}
 
 }  // extern "C"

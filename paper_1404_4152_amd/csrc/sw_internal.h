@@ -25,12 +25,14 @@ constexpr int kThrI16 = 32767;   // saturating int16
 
 enum Tier : int { TIER_F16X2 = 1, TIER_I16X2 = 2 };
 
-// Per-call description of the queries on the device.
+// Per-call description of the queries on the device, indexed by query slot.
+// Slot q's profile is R rows x mpad[q] int8 at qp[q]; its scores go to row q
+// of the score matrix.
 struct QuerySet {
-    const int8_t *qp;        // profiles: query q at qp + qp_off[q], R rows x mpad[q] cols
-    const int64_t *qp_off;
+    const int8_t *const *qp;
     const int32_t *mpad;     // padded length (multiple of kQPad)
     const int32_t *qlen;     // real length
+    const int32_t *gap;      // alpha, beta of slot q at gap[2q], gap[2q+1]
 };
 
 struct InterArgs {
@@ -45,7 +47,6 @@ struct InterArgs {
     int32_t *counter;        // work-queue head, zero before launch
     QuerySet qs;
     int32_t R;
-    int32_t alpha, beta;     // already clamped for the tier
     int32_t thr;             // a lane whose best reaches thr is flagged
     uint32_t *scratch;       // boundary columns: per (slot, wave) max_rows * 64 * 2 dwords
     int32_t max_rows;
@@ -65,12 +66,15 @@ struct IntraArgs {
     int32_t *counter;
     QuerySet qs;
     int32_t R;
-    int32_t alpha, beta;
     int32_t *pass_scratch;   // per (slot, wave): (max_len_pad) x 2 int32
     int64_t max_len_pad;     // rows per scratch slot (>= longest subject rounded to 64, + 128)
     int32_t *scores;
     int64_t n_seqs;
 };
+
+// Raise the dynamic-LDS limit of every kernel variant (once per device, before
+// any launch or stream capture).
+hipError_t prepare_kernels();
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
@@ -92,7 +96,9 @@ struct TopkWork {
     int32_t *cand_i;     // nq * k
 };
 constexpr int kTopkBlocks = 256;
-hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, int32_t k,
-                       const TopkWork &w, int32_t *top_s, int64_t *top_i, hipStream_t st);
+// rows: nq row indices into `scores` (nullptr = rows 0..nq-1).
+hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, const int32_t *rows,
+                       int32_t k, const TopkWork &w, int32_t *top_s, int64_t *top_i,
+                       hipStream_t st);
 
 }  // namespace swmi

@@ -258,7 +258,9 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
-    const L ops(a.alpha, a.beta);
+    // Penalties above the tier's range only change values that are floored
+    // to 0 anyway, so they are clamped to it.
+    constexpr int kCap = TIER == TIER_I16X2 ? 32767 : 2048;
     uint32_t *wsc = a.scratch + ((size_t)(blockIdx.x * W + w) * (size_t)a.max_rows) * 128 + lane * 8;
 
     for (;;) {
@@ -267,12 +269,13 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
         const int it = s_item;
         if (it >= a.n_items) break;
         const int q = a.item_q[it];
+        const L ops(min(a.qs.gap[2 * q], kCap), min(a.qs.gap[2 * q + 1], kCap));
         const int g = a.item_g[it] + w;
         const bool active = g < a.n_groups;
         const int rows = active ? a.grp_rows[g] : 0;
         const int mp = a.qs.mpad[q];
         const int nstrips = mp / T;
-        const int8_t *qp = a.qs.qp + a.qs.qp_off[q];
+        const int8_t *qp = a.qs.qp[q];
         const uint16_t *codes = a.codes + (active ? a.grp_base[g] : 0) + lane * 4;
         V best = L::zero();
 
@@ -350,9 +353,6 @@ template <int T, int W, int TIER>
 static hipError_t launch_inter_t(const InterArgs &a, int grid, hipStream_t st) {
     int magic = (65536 + a.R - 1) / a.R;
     const int lds = inter_lds_bytes(a.R, T);
-    hipError_t e = hipFuncSetAttribute((const void *)inter_kernel<T, W, TIER>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((inter_kernel<T, W, TIER>), dim3(grid), dim3(W * 64), lds, st, a, magic);
     return hipGetLastError();
 }
@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
         const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
         const int mp = a.qs.mpad[q];
         const int npass = (a.qs.qlen[q] + PW - 1) / PW;
-        const int8_t *qp = a.qs.qp + a.qs.qp_off[q];
+        const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
+        const int8_t *qp = a.qs.qp[q];
         int best = 0;
 
         for (int p = 0; p < npass; ++p) {
@@ -503,7 +504,7 @@ __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
                 fH = shl1(fH, fH);
                 fF = shl1(fF, fF);
                 const uint2 *pr = (const uint2 *)(prof + r * RS + lane * T);
-                intra_row<T>(H, E, pr, hb_prev, fin, a.alpha, a.beta, best, hout, fout);
+                intra_row<T>(H, E, pr, hb_prev, fin, alpha, beta, best, hout, fout);
                 hb_prev = hin;
                 if (has_out) {
                     cH = shl1(hout, cH);
@@ -529,9 +530,6 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 template <int T, int W>
 static hipError_t launch_intra_t(const IntraArgs &a, int grid, hipStream_t st) {
     const int lds = intra_lds_bytes(a.R, T);
-    hipError_t e = hipFuncSetAttribute((const void *)intra_kernel<T, W>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((intra_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
     return hipGetLastError();
 }
@@ -575,15 +573,15 @@ __global__ void topk_init(int32_t *state, uint32_t *hist, int32_t k) {
     }
 }
 
-__global__ void topk_hist(const int32_t *scores, int64_t n, int pass, const int32_t *state,
-                          uint32_t *hist) {
+__global__ void topk_hist(const int32_t *scores, int64_t n, const int32_t *rows, int pass,
+                          const int32_t *state, uint32_t *hist) {
     __shared__ uint32_t h[256];
     const int q = blockIdx.y;
     for (int b = threadIdx.x; b < 256; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const uint32_t prefix = (uint32_t)state[q * 4 + 0];
     const int shift = 24 - 8 * pass;
-    const int32_t *row = scores + (size_t)q * n;
+    const int32_t *row = scores + (size_t)(rows ? rows[q] : q) * n;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t v = (uint32_t)row[i];
@@ -615,15 +613,15 @@ __global__ void topk_select(int32_t *state, uint32_t *hist, int nq) {
     for (int b = 0; b < 256; ++b) h[b] = 0;
 }
 
-__global__ void topk_gather(const int32_t *scores, int64_t n, int32_t *state, int32_t *eqcnt,
-                            int32_t *cs, int32_t *ci, int32_t k) {
+__global__ void topk_gather(const int32_t *scores, int64_t n, const int32_t *rows, int32_t *state,
+                            int32_t *eqcnt, int32_t *cs, int32_t *ci, int32_t k) {
     __shared__ int32_t red[32];
     const int q = blockIdx.y;
     const uint32_t theta = (uint32_t)state[q * 4 + 0];
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    const int32_t *row = scores + (size_t)q * n;
+    const int32_t *row = scores + (size_t)(rows ? rows[q] : q) * n;
     int cnt = 0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
         const uint32_t v = (uint32_t)row[i];
@@ -647,8 +645,9 @@ __global__ void topk_gather(const int32_t *scores, int64_t n, int32_t *state, in
     }
 }
 
-__global__ void topk_gather_eq(const int32_t *scores, int64_t n, const int32_t *state,
-                               const int32_t *eqcnt, int32_t *cs, int32_t *ci, int32_t k) {
+__global__ void topk_gather_eq(const int32_t *scores, int64_t n, const int32_t *rows,
+                               const int32_t *state, const int32_t *eqcnt, int32_t *cs,
+                               int32_t *ci, int32_t k) {
     __shared__ int32_t wsum[16];
     __shared__ int32_t s_base;
     const int q = blockIdx.y;
@@ -666,7 +665,7 @@ __global__ void topk_gather_eq(const int32_t *scores, int64_t n, const int32_t *
     const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     const int64_t lo = blockIdx.x * chunk;
     const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    const int32_t *row = scores + (size_t)q * n;
+    const int32_t *row = scores + (size_t)(rows ? rows[q] : q) * n;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int64_t t0 = lo; t0 < hi; t0 += blockDim.x) {
         const int64_t i = t0 + threadIdx.x;
@@ -726,25 +725,46 @@ __global__ void topk_final(const int32_t *state, const int32_t *eqcnt, int nblk,
     }
 }
 
-hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, int32_t k,
-                       const TopkWork &w, int32_t *top_s, int64_t *top_i, hipStream_t st) {
+hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, const int32_t *rows,
+                       int32_t k, const TopkWork &w, int32_t *top_s, int64_t *top_i,
+                       hipStream_t st) {
     if (nq <= 0) return hipSuccess;
     hipLaunchKernelGGL(topk_init, dim3(nq), dim3(256), 0, st, w.state, w.hist, k);
     int64_t hb = (n + 2047) / 2048;
     if (hb < 1) hb = 1;
     if (hb > 128) hb = 128;
     for (int pass = 0; pass < 4; ++pass) {
-        hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb, nq), dim3(256), 0, st, scores, n, pass,
-                           w.state, w.hist);
+        hipLaunchKernelGGL(topk_hist, dim3((unsigned)hb, nq), dim3(256), 0, st, scores, n, rows,
+                           pass, w.state, w.hist);
         hipLaunchKernelGGL(topk_select, dim3((nq + 63) / 64), dim3(64), 0, st, w.state, w.hist, nq);
     }
-    hipLaunchKernelGGL(topk_gather, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n, w.state,
-                       w.eqcnt, w.cand_s, w.cand_i, k);
-    hipLaunchKernelGGL(topk_gather_eq, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n,
+    hipLaunchKernelGGL(topk_gather, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n, rows,
+                       w.state, w.eqcnt, w.cand_s, w.cand_i, k);
+    hipLaunchKernelGGL(topk_gather_eq, dim3(kTopkBlocks, nq), dim3(256), 0, st, scores, n, rows,
                        w.state, w.eqcnt, w.cand_s, w.cand_i, k);
     hipLaunchKernelGGL(topk_final, dim3(nq), dim3(256), (size_t)k * 8, st, w.state, w.eqcnt,
                        kTopkBlocks, w.cand_s, w.cand_i, k, top_s, top_i);
     return hipGetLastError();
+}
+
+hipError_t prepare_kernels() {
+    const void *ks[] = {
+        (const void *)inter_kernel<16, 4, TIER_F16X2>, (const void *)inter_kernel<16, 8, TIER_F16X2>,
+        (const void *)inter_kernel<32, 4, TIER_F16X2>, (const void *)inter_kernel<32, 6, TIER_F16X2>,
+        (const void *)inter_kernel<32, 8, TIER_F16X2>, (const void *)inter_kernel<64, 4, TIER_F16X2>,
+        (const void *)inter_kernel<16, 4, TIER_I16X2>, (const void *)inter_kernel<16, 8, TIER_I16X2>,
+        (const void *)inter_kernel<32, 4, TIER_I16X2>, (const void *)inter_kernel<32, 6, TIER_I16X2>,
+        (const void *)inter_kernel<32, 8, TIER_I16X2>, (const void *)inter_kernel<64, 4, TIER_I16X2>,
+        (const void *)intra_kernel<4, 1>,  (const void *)intra_kernel<8, 1>,
+        (const void *)intra_kernel<16, 1>, (const void *)intra_kernel<4, 4>,
+        (const void *)intra_kernel<8, 4>,  (const void *)intra_kernel<16, 4>,
+    };
+    for (const void *k : ks) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024 - 64);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace swmi
