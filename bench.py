@@ -1,23 +1,32 @@
 """Benchmark: exact Smith-Waterman protein database search on one MI355X.
 
-Default workload (plain search at scale): 20 queries of lengths 144..5,478,
-searched one at a time (top-10 each) against a synthetic database of 2M
+Headline (`value`): plain search at scale.  20 queries of lengths 144..5,478
+are searched one at a time (top-10 each) against a synthetic database of 2M
 length-sorted protein sequences (log-normal lengths, mean 350, <= 35,000,
-~0.70G residues), BLOSUM62-style matrix, beta = 12, alpha = 2.
+~0.70G residues), with a BLOSUM62-style matrix, beta = 12 and alpha = 2.
+One step = the whole hot path for every query: query profile,
+lane-per-subject kernel, overflow recompute, wave-per-pair kernel for the
+long tail, top-k.  The database is resident in HBM before timing starts.
+It is opened once, as the paper's offline index is built once.
 
-One step = the whole hot path for every query: query profile, lane-per-subject
-kernel, overflow recompute, wave-per-pair kernel for the long tail, top-k.
-The database is resident in HBM before timing starts (opened once, as the
-paper's offline index is built once).
+Also measured in the same run, as sub-objects of the JSON line:
+  batched: 512 queries (50..1,500) against 500k subjects in one fused launch
+           replayed from a captured HIP graph;
+  served:  Poisson arrivals against a resident 5M-subject database
+           (continuous batching), p50/p99 latency and sustained GCUPS, at the
+           configured 50 queries/s (over a short window) and at ~70% of the
+           measured capacity.
 
-Prints one JSON line.  `value` is GCUPS = sum|Q| * sum|S| / seconds.
+Prints one JSON line.  GCUPS = sum|Q| * sum|S| / seconds.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -30,13 +39,17 @@ CUS, CLOCK_GHZ = 256, 2.4
 PEAK_LANE_OPS = CUS * 64 * CLOCK_GHZ * 1e9          # 32-bit VALU lane-ops/s (39.3 T)
 PEAK_HALF_OPS = 2 * PEAK_LANE_OPS                    # packed 16-bit lane-ops/s (78.6 T)
 OPS_PER_CELL = 7.5                                   # add, max3, sub, 2x(sub+max3), max3/2
+PEAK_GCUPS_F16X2 = PEAK_HALF_OPS / OPS_PER_CELL / 1e9
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def measured_traffic(workload, plan_overridden):
     """HBM bytes per launch of the lane-per-subject kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter passes, if they were taken on this exact
     kernel source and workload; None otherwise."""
-    import hashlib
     rec_path = os.path.join(ROOT, "profiles", f"inter_kernel_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_1404_4152_amd", "csrc", "sw_kernels.hip")
     if plan_overridden or not os.path.exists(rec_path):
@@ -45,10 +58,6 @@ def measured_traffic(workload, plan_overridden):
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
-
-
-def log(msg):
-    print(msg, file=sys.stderr, flush=True)
 
 
 def cpu_baseline(workload, res, off, queries, M, target_s=15.0):
@@ -80,31 +89,7 @@ def cpu_baseline(workload, res, off, queries, M, target_s=15.0):
                       f"({cells:.3e} cells, {dt:.1f} s)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="plain_scale",
-                    choices=["plain_scale", "plain_small", "long_tail", "batched"])
-    ap.add_argument("--k", type=int, default=10)
-    ap.add_argument("--tier", type=int, default=0)
-    ap.add_argument("--strip", type=int, default=0)
-    ap.add_argument("--waves", type=int, default=0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
-              "is a design, not a build, in this repository", file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-    import paper_1404_4152_amd as swmi
-    import synthdata as sd
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    torch.cuda.set_device(0)
+def run_plain(args, swmi, sd, torch):
     w = sd.WORKLOADS[args.workload]
     t0 = time.perf_counter()
     res, off = w.db()
@@ -116,67 +101,39 @@ def main():
     t0 = time.perf_counter()
     db = swmi.Database(res, off, 20, device=0)
     log(f"[bench] database opened (sorted, packed, uploaded) in {time.perf_counter() - t0:.1f}s")
-    if args.tier or args.strip or args.waves:
+    overridden = bool(args.tier or args.strip or args.waves)
+    if overridden:
         db.set_opts(tier=args.tier, strip=args.strip, waves=args.waves)
-    stream = torch.cuda.current_stream()
-    sptr = stream.cuda_stream
-
+    # kernels, HIP events and torch's synchronisation share torch's current stream
+    sptr = torch.cuda.current_stream().cuda_stream
     sum_q = sum(len(q) for q in queries)
     cells_step = sum_q * int(len(res))
-    batched = args.workload == "batched"
 
     def step():
-        inter_ms, kern_ms, n_inter, recomputed, padded = 0.0, 0.0, 0, 0, 0
-        if batched:
-            swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, args.k, stream=sptr)
-            st = db.stats()
-            return st["inter_ms"], st["kernel_ms"], 1, st["recomputed_pairs"], st["padded_cells"], [st]
         sts = []
         for q in queries:
             swmi.sw_db_topk(db.h, q, M, w.alpha, w.beta, args.k, stream=sptr)
-            st = db.stats()
-            sts.append(st)
-            inter_ms += st["inter_ms"]
-            kern_ms += st["kernel_ms"]
-            n_inter += 1
-            recomputed += st["recomputed_pairs"]
-            padded += st["padded_cells"]
-        return inter_ms, kern_ms, n_inter, recomputed, padded, sts
+            sts.append(db.stats())
+        return sts
 
     for i in range(args.warmup):
         step()
         log(f"[bench] warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
-    tot_inter, tot_kern, tot_launch, tot_recomp = 0.0, 0.0, 0, 0
-    per_query = None
+    all_sts = []
     t = time.perf_counter()
     for i in range(args.steps):
-        a, b, c, d, padded, sts = step()
-        tot_inter += a
-        tot_kern += b
-        tot_launch += c
-        tot_recomp += d
-        per_query = sts
+        all_sts += step()
         log(f"[bench] step {i + 1}/{args.steps} done ({time.perf_counter() - t:.1f}s)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    db.close()
     gcups = cells_step * args.steps / dt / 1e9
-
-    # dominant kernel: the lane-per-subject kernel (HIP events on its stream)
-    st0 = per_query[0]
-    inter_cells = sum(x["inter_cells"] for x in per_query)      # one step
-    avg_launch_ms = tot_inter / max(tot_launch, 1)
-    ops_per_launch = OPS_PER_CELL * inter_cells / len(per_query)
-    achieved = ops_per_launch / (avg_launch_ms / 1e3) / 1e12
-    peak = PEAK_HALF_OPS / 1e12
-    traffic = measured_traffic(w.name, bool(args.tier or args.strip or args.waves))
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
-                "unit": "Tops/s", "frac": round(achieved / peak, 4),
-                "traffic": round(traffic) if traffic else None, "traffic_unit": "bytes per launch",
-                "kernel": "inter_kernel (f16x2)", "ops_per_cell": OPS_PER_CELL,
-                "avg_launch_ms": round(avg_launch_ms, 3)}
+    st0 = all_sts[0]
+    # dominant kernel: the lane-per-subject kernel, one launch per query
+    inter = [s for s in all_sts if s["inter_cells"] > 0]
     out = {
-        "metric": "GCUPS (plain per-query search, top-10), fraction of packed-16-bit VALU peak",
+        "metric": "GCUPS + % integer-VALU peak (batched/served vs plain); p50/p99 query latency",
         "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16x2+i32",
@@ -185,14 +142,163 @@ def main():
                    "queries": len(queries), "sum_query_len": sum_q, "k": args.k,
                    "alpha": w.alpha, "beta": w.beta, "tier": st0["tier"], "strip": st0["strip"],
                    "waves": st0["waves"], "parallelism": "single GPU"},
-        "kernel_gcups": round(cells_step * args.steps / (tot_kern / 1e3) / 1e9, 2),
-        "recomputed_pairs_per_step": tot_recomp // max(args.steps, 1),
-        "roofline": roofline,
+        "frac_of_f16x2_peak_gcups": round(gcups / PEAK_GCUPS_F16X2, 4),
+        "kernel_gcups": round(cells_step * args.steps /
+                              (sum(s["kernel_ms"] for s in all_sts) / 1e3) / 1e9, 2),
+        "recomputed_pairs_per_step": sum(s["recomputed_pairs"] for s in all_sts) // max(args.steps, 1),
     }
+    if inter:
+        avg_launch_ms = sum(s["inter_ms"] for s in inter) / len(inter)
+        ops_per_launch = OPS_PER_CELL * sum(s["inter_cells"] for s in inter) / len(inter)
+        achieved = ops_per_launch / (avg_launch_ms / 1e3) / 1e12
+        peak = PEAK_HALF_OPS / 1e12
+        traffic = measured_traffic(w.name, bool(args.tier or args.strip or args.waves))
+        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+                           "unit": "Tops/s", "frac": round(achieved / peak, 4),
+                           "traffic": round(traffic) if traffic else None,
+                           "traffic_unit": "bytes per launch", "kernel": "inter_kernel (f16x2)",
+                           "ops_per_cell": OPS_PER_CELL, "avg_launch_ms": round(avg_launch_ms, 3)}
+    return out, (w, res, off, queries, M)
+
+
+def run_batched(args, swmi, sd, torch):
+    w = sd.WORKLOADS["batched"]
+    res, off = w.db()
+    queries = w.queries()
+    M = w.matrix()
+    db = swmi.Database(res, off, 20, device=0)
+    sptr = torch.cuda.current_stream().cuda_stream
+    cells = sum(len(q) for q in queries) * int(len(res))
+    log(f"[bench] batched: {len(queries)} queries x {len(off) - 1} subjects ({cells:.3e} cells)")
+    swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, 10, stream=sptr)   # warmup + capture
+    torch.cuda.synchronize()
+    steps = max(1, args.batched_steps)
+    kern = 0.0
+    t = time.perf_counter()
+    for _ in range(steps):
+        swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, 10, stream=sptr)
+        st = db.stats()
+        kern += st["kernel_ms"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
     db.close()
+    g = cells * steps / dt / 1e9
+    log(f"[bench] batched done: {g:.1f} GCUPS")
+    return {"workload": w.name, "queries": len(queries), "subjects": len(off) - 1,
+            "residues": int(len(res)), "k": 10, "graphed": bool(st["graphed"]),
+            "gcups": round(g, 2), "kernel_gcups": round(cells * steps / (kern / 1e3) / 1e9, 2),
+            "frac_of_f16x2_peak_gcups": round(g / PEAK_GCUPS_F16X2, 4),
+            "ms_per_batch": round(dt / steps * 1e3, 1), "tier": st["tier"], "strip": st["strip"],
+            "waves": st["waves"]}
+
+
+def serve_phase(swmi, srv, M, alpha, beta, queries, arrivals, total_res):
+    """Open-loop arrivals; returns latency percentiles and sustained GCUPS."""
+    lat, qms = [], []
+    cells = 0
+    lock = threading.Lock()
+    t0 = time.perf_counter()
+
+    def collector(t):
+        _, _, st = swmi.sw_server_wait(srv, t, 10)
+        with lock:
+            lat.append(st["total_ms"])
+            qms.append(st["queue_ms"])
+
+    threads = []
+    for q, a in zip(queries, arrivals):
+        now = time.perf_counter() - t0
+        if a > now:
+            time.sleep(a - now)
+        t = swmi.sw_server_submit(srv, q, M, alpha, beta, 10)
+        cells += len(q) * total_res
+        th = threading.Thread(target=collector, args=(t,))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    span = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"requests": len(queries), "offered_per_s": round(len(queries) / max(arrivals[-1], 1e-9), 2),
+            "p50_ms": round(float(np.percentile(lat, 50)), 1),
+            "p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "mean_queue_ms": round(float(np.mean(qms)), 1),
+            "sustained_gcups": round(cells / span / 1e9, 1), "span_s": round(span, 2)}
+
+
+def run_served(args, swmi, sd, torch):
+    w = sd.WORKLOADS["serving"]
+    t0 = time.perf_counter()
+    res, off = w.db()
+    M = w.matrix()
+    db = swmi.Database(res, off, 20, device=0)
+    total = int(len(res))
+    log(f"[bench] serving database: {len(off) - 1} subjects, {total} residues, opened in "
+        f"{time.perf_counter() - t0:.1f}s")
+    srv = swmi.sw_server_start(db.h, memory_budget=8 << 30, max_active=64)
+    out = {"workload": w.name, "subjects": len(off) - 1, "residues": total, "k": 10}
+    try:
+        # phase 1: the configured rate (50 queries/s) over a short window
+        arr = sd.poisson_arrivals(50.0, args.serve_seconds, seed=sd.SEED_ARRIVALS)
+        qs = sd.serving_queries(len(arr), seed=sd.SEED_QUERIES + 20)
+        log(f"[bench] serving phase 1: {len(arr)} requests at 50/s")
+        p1 = serve_phase(swmi, srv, M, w.alpha, w.beta, qs, arr, total)
+        out["at_50_per_s"] = p1
+        # capacity from phase 1, then ~70% of it
+        mean_cells = float(np.mean([len(q) for q in qs])) * total
+        rate = max(0.5, 0.7 * p1["sustained_gcups"] * 1e9 / mean_cells)
+        arr2 = sd.poisson_arrivals(rate, args.serve_seconds * 1.5, seed=sd.SEED_ARRIVALS + 1)
+        qs2 = sd.serving_queries(len(arr2), seed=sd.SEED_QUERIES + 21)
+        log(f"[bench] serving phase 2: {len(arr2)} requests at {rate:.1f}/s")
+        p2 = serve_phase(swmi, srv, M, w.alpha, w.beta, qs2, arr2, total)
+        p2["rate_per_s"] = round(rate, 2)
+        out["at_70pct_capacity"] = p2
+    finally:
+        swmi.sw_server_stop(srv)
+        db.close()
+    log("[bench] serving done")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="plain_scale",
+                    choices=["plain_scale", "plain_small", "long_tail"])
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--tier", type=int, default=0)
+    ap.add_argument("--strip", type=int, default=0)
+    ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=1)
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=4.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is "
+              "a design in this repository, not a build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1404_4152_amd as swmi
+    import synthdata as sd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    out, (w, res, off, queries, M) = run_plain(args, swmi, sd, torch)
+    if not args.no_batched and args.workload == "plain_scale":
+        b = run_batched(args, swmi, sd, torch)
+        b["vs_plain_gcups"] = round(b["gcups"] / out["value"], 3)
+        out["batched"] = b
+    if not args.no_served and args.workload == "plain_scale":
+        out["served"] = run_served(args, swmi, sd, torch)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a sample")
-        out["cpu_baseline"] = cpu_baseline(w, res, off, queries, M, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(w, res, off, queries, M, target_s=args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -137,6 +137,9 @@ struct Plan {
 };
 
 constexpr int kIntraWaves = 4;   // waves per workgroup of the wave-per-pair kernel (long list)
+// Subjects longer than this never go into a lane-per-subject group: one lane
+// would hold its SIMD too long and its boundary buffer would be large.
+constexpr int64_t kGroupMaxLen = 8192;
 
 int intra_T_for(int64_t max_qlen) {
     if (max_qlen <= 256) return 4;
@@ -179,10 +182,13 @@ struct sw_db {
     std::vector<int32_t> grp_rows;    // host copy, ascending
     int64_t inter_res = 0;            // residues in groups
     int64_t inter_padded_rows = 0;    // sum of rows * 128
-    // long list (caller ids), longest first
+    std::vector<int32_t> grp_ids;     // host copy: caller ids of each group's 128 slots
+    std::vector<int64_t> grp_res_prefix;  // residues in groups [0, g)
+    // long list (caller ids), longest first: subjects too long for any group
     std::vector<int32_t> long_ids;
     int64_t long_res = 0;
     int64_t long_threshold = 0;
+    bool fixed_cut = false;           // the caller fixed the split at open
     // device copies
     DevBuf d_res, d_off, d_codes, d_grp_base, d_grp_rows, d_grp_ids;
     // per-call workspaces (plain and batched searches)
@@ -257,13 +263,53 @@ void write_profile(int8_t *dst, const uint8_t *q, int64_t qlen, int32_t mpad, co
     }
 }
 
+// Which groups a search runs lane-per-subject.  A wave works through one
+// group per item, so the longest group must not hold its wave for longer than
+// the average wave's share of the whole search, or it alone sets the
+// makespan; longer groups go to the wave-per-pair kernel instead.  With many
+// queries the share is large and every group stays lane-per-subject.
+// Returns the number of leading groups (a multiple of the block size) to run
+// lane-per-subject, and appends the routed subjects to `long_ids`.
+int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> &mpad,
+                  int resident_waves, std::vector<int32_t> &long_ids) {
+    long_ids = db->long_ids;
+    const int W = plan.waves;
+    if (db->n_groups == 0) return 0;
+    int64_t g_cut = db->n_groups;
+    if (!db->fixed_cut) {
+        double strips = 0, max_strips = 1;
+        for (int32_t m : mpad) {
+            strips += m / plan.strip;
+            max_strips = std::max<double>(max_strips, m / plan.strip);
+        }
+        const double rows = (double)db->inter_padded_rows / kGroup;
+        const double share = strips * rows / std::max(resident_waves, 1) / max_strips;
+        const int64_t rows_cut = std::max<int64_t>(1024, (int64_t)share);
+        g_cut = std::upper_bound(db->grp_rows.begin(), db->grp_rows.end(), (int32_t)std::min<int64_t>(rows_cut, INT32_MAX)) -
+                db->grp_rows.begin();
+        if (g_cut < db->n_groups) g_cut = g_cut / W * W;
+    }
+    std::vector<int32_t> routed;
+    for (int64_t g = db->n_groups - 1; g >= g_cut; --g)
+        for (int x = kGroup - 1; x >= 0; --x) {
+            const int32_t id = db->grp_ids[(size_t)g * kGroup + x];
+            if (id >= 0) routed.push_back(id);
+        }
+    // longest first: the fixed long list precedes every routed group
+    std::stable_sort(routed.begin(), routed.end(),
+                     [&](int32_t a, int32_t b) { return db->len[a] > db->len[b]; });
+    long_ids.insert(long_ids.end(), routed.begin(), routed.end());
+    return g_cut;
+}
+
 // Lane-per-subject items for `slots` against group blocks [b0, b1) and, if
-// with_long, wave-per-pair items against the long list; each list longest
-// first (the GPU analogue of the guided schedule of section III.A).
+// with_long, wave-per-pair items against `long_ids`; each list longest first
+// (the GPU analogue of the guided schedule of section III.A).
 // stride > 1 keeps every stride-th block only (autotuner sampling).
 void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &slots,
                  const std::vector<int32_t> &mpad, const std::vector<int64_t> &qlen, int64_t b0,
-                 int64_t b1, bool with_long, int64_t stride, Items &it) {
+                 int64_t b1, bool with_long, const std::vector<int32_t> &long_ids, int64_t stride,
+                 Items &it) {
     const int W = plan.waves;
     std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> v;
     v.reserve((size_t)slots.size() * (size_t)std::max<int64_t>(b1 - b0, 0));
@@ -286,13 +332,13 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     it.intra_q.clear();
     it.intra_ids.clear();
     if (!with_long) return;
-    const int64_t nlong = (int64_t)db->long_ids.size();
+    const int64_t nlong = (int64_t)long_ids.size();
     const int64_t nlblk = (nlong + kIntraWaves - 1) / kIntraWaves;
     std::vector<std::pair<int64_t, std::pair<int32_t, int64_t>>> u;
     for (size_t x = 0; x < slots.size(); ++x)
         for (int64_t bk = 0; bk < nlblk; ++bk) {
             if (stride > 1 && (bk % stride) != 0) continue;
-            u.push_back({db->len[db->long_ids[bk * kIntraWaves]] * qlen[x], {slots[x], bk}});
+            u.push_back({db->len[long_ids[bk * kIntraWaves]] * qlen[x], {slots[x], bk}});
         }
     std::stable_sort(u.begin(), u.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
     it.intra_q.resize(u.size());
@@ -301,7 +347,7 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
         it.intra_q[i] = u[i].second.first;
         for (int w = 0; w < kIntraWaves; ++w) {
             const int64_t x = u[i].second.second * kIntraWaves + w;
-            it.intra_ids[i * kIntraWaves + w] = x < nlong ? db->long_ids[x] : -1;
+            it.intra_ids[i * kIntraWaves + w] = x < nlong ? long_ids[x] : -1;
         }
     }
 }
@@ -333,6 +379,7 @@ struct PassBufs {
     int64_t ovf_cap = 0;
     int32_t *counters = nullptr;   // inter head, overflow count, long head, recompute head
     uint32_t *scr_inter = nullptr;
+    int32_t scr_rows = 0;          // rows per wave slot of scr_inter
     int32_t *scr_intra = nullptr;
 };
 
@@ -358,7 +405,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         a.R = db->R;
         a.thr = L.plan.thr;
         a.scratch = b.scr_inter;
-        a.max_rows = db->max_rows;
+        a.max_rows = b.scr_rows;
         a.scores = b.scores;
         a.n_seqs = db->n_seqs;
         a.ovf_q = b.ovf_q;
@@ -472,12 +519,18 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
 
     std::vector<int32_t> slots(nq);
     std::iota(slots.begin(), slots.end(), 0);
+    std::vector<int32_t> long_ids;
+    const int resident = inter_max_grid(db->R, plan.strip, plan.waves) * plan.waves;
+    const int64_t g_cut = route_cut(db, plan, mpad, resident, long_ids);
     Items it;
-    const int64_t nblk = (db->n_groups + plan.waves - 1) / plan.waves;
-    build_items(db, plan, slots, mpad, qlen, 0, nblk, true, item_stride, it);
+    const int64_t nblk = (g_cut + plan.waves - 1) / plan.waves;
+    build_items(db, plan, slots, mpad, qlen, 0, nblk, true, long_ids, item_stride, it);
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     if (n_inter > INT32_MAX || n_intra > INT32_MAX) return fail(SW_EINVAL, "batch too large");
     const Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra);
+    const int32_t rows_alloc = g_cut > 0 ? db->grp_rows[g_cut - 1] : 0;
+    int64_t long_res = 0;
+    for (int32_t id : long_ids) long_res += db->len[id];
 
     // ---- device workspaces ----
     const StageLayout sl = stage_layout(nq, prof_bytes, it);
@@ -486,7 +539,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     TRY(db->w_counters.reserve(256));
     TRY(db->w_ovf.reserve((size_t)nq * n * 8 + 8));
     if (n_inter > 0)
-        TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * db->max_rows * 512));
+        TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * rows_alloc * 512));
     const int64_t intra_slots = std::max<int64_t>((int64_t)L.grid_long * kIntraWaves, L.grid_ovf);
     TRY(db->w_scr_intra.reserve((size_t)intra_slots * intra_scratch_rows(db) * 8));
     if (k > 0) {
@@ -538,6 +591,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     pb.ovf_cap = (int64_t)nq * n;
     pb.counters = db->w_counters.as<int32_t>();
     pb.scr_inter = db->w_scr_inter.as<uint32_t>();
+    pb.scr_rows = rows_alloc;
     pb.scr_intra = db->w_scr_intra.as<int32_t>();
     int64_t *d_ti = k > 0 ? db->w_top.as<int64_t>() : nullptr;
     int32_t *d_ts = d_ti ? (int32_t *)(d_ti + (size_t)nq * k) : nullptr;
@@ -556,8 +610,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
         // Every kernel argument of the pass is fixed by this key; what changes
         // between calls of one shape (profiles, items) arrives by the staging copy.
         char key[512];
-        snprintf(key, sizeof key, "%d|%d|%d|%d|%d|%d|%lld|%lld|%d|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%p",
-                 nq, k, plan.tier, plan.strip, plan.waves, plan.thr, (long long)n_inter,
+        snprintf(key, sizeof key, "%d|%d|%d|%d|%d|%d|%d|%lld|%lld|%d|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%p",
+                 rows_alloc, nq, k, plan.tier, plan.strip, plan.waves, plan.thr, (long long)n_inter,
                  (long long)n_intra, L.Ti, L.grid_inter, L.grid_long, L.grid_ovf, (void *)ds,
                  (void *)pb.scores, (void *)pb.ovf_q, (void *)pb.counters, (void *)pb.scr_inter,
                  (void *)pb.scr_intra, db->w_topk.p, (void *)d_ti);
@@ -614,13 +668,14 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     s = sw_stats{};
     s.cells = sum_qlen * db->total_res;
     int64_t padded = 0;
+    int64_t inter_rows = 0;
+    for (int64_t g = 0; g < g_cut; ++g) inter_rows += (int64_t)db->grp_rows[g] * kGroup;
     for (int32_t q = 0; q < nq; ++q)
-        padded += (int64_t)mpad[q] * db->inter_padded_rows +
-                  round_up(qlen[q], 64LL * L.Ti) * db->long_res;
+        padded += (int64_t)mpad[q] * inter_rows + round_up(qlen[q], 64LL * L.Ti) * long_res;
     s.padded_cells = padded;
-    s.inter_cells = sum_qlen * db->inter_res;
+    s.inter_cells = sum_qlen * db->grp_res_prefix[g_cut];
     s.recomputed_pairs = ctr_h[1];
-    s.intra_pairs = (int64_t)db->long_ids.size() * nq;
+    s.intra_pairs = (int64_t)long_ids.size() * nq;
     s.kernel_ms = ms_k;
     s.inter_ms = ms_i;
     s.total_ms = now_ms() - t_start;
@@ -728,7 +783,7 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
                 }
                 ms = std::min(ms, db->last.inter_ms);
             }
-            const double gc = (double)L * db->inter_res / stride / (ms * 1e6);
+            const double gc = (double)db->last.inter_cells / stride / (ms * 1e6);
             if (gc > best) {
                 best = gc;
                 best_plan = cand;
@@ -780,6 +835,9 @@ struct sw_server {
     sw_server_opts opts{};
     Plan plan;
     int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
+    int64_t g_cut = 0;
+    int32_t scr_rows = 0;
+    std::vector<int32_t> long_ids;   // wave-per-pair subjects, longest first
     bool has_long = false;
     int32_t slots = 0;
     // device state
@@ -810,12 +868,19 @@ int server_setup(sw_server *s) {
     HIPX(hipSetDevice(db->device));
     s->plan = plan_for(db, 512);
     const int W = s->plan.waves;
-    s->blocks = (db->n_groups + W - 1) / W;
+    {
+        // route as if half the slots held 400-residue queries
+        const int slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
+        std::vector<int32_t> mp(std::max(1, slots / 2), 448);
+        const int resident = inter_max_grid(db->R, s->plan.strip, W) * W;
+        s->g_cut = route_cut(db, s->plan, mp, resident, s->long_ids);
+    }
+    s->blocks = (s->g_cut + W - 1) / W;
     const int64_t cb = s->opts.chunk_groups > 0 ? (s->opts.chunk_groups + W - 1) / W
                                                 : std::max<int64_t>(1, (s->blocks + 15) / 16);
     s->chunk_blocks = std::max<int64_t>(1, cb);
     s->n_chunks = s->blocks > 0 ? (s->blocks + s->chunk_blocks - 1) / s->chunk_blocks : 0;
-    s->has_long = !db->long_ids.empty();
+    s->has_long = !s->long_ids.empty();
     s->n_pos = s->n_chunks + (s->has_long ? 1 : 0);
     s->slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
     if (s->opts.memory_budget <= 0) s->opts.memory_budget = (int64_t)1 << 30;
@@ -826,7 +891,7 @@ int server_setup(sw_server *s) {
     const int64_t n = db->n_seqs;
     // the largest pass: every slot against one chunk, or against the long list
     const int64_t inter_items = (int64_t)s->slots * s->chunk_blocks;
-    const int64_t nlblk = ((int64_t)db->long_ids.size() + kIntraWaves - 1) / kIntraWaves;
+    const int64_t nlblk = ((int64_t)s->long_ids.size() + kIntraWaves - 1) / kIntraWaves;
     const int64_t intra_items = (int64_t)s->slots * nlblk;
     s->L = launch_config(db, s->plan, 1 << 14, std::max<int64_t>(inter_items, 1),
                          std::max<int64_t>(intra_items, 1));
@@ -837,8 +902,9 @@ int server_setup(sw_server *s) {
     const int64_t chunk_subj = s->chunk_blocks * W * kGroup;
     TRY(s->d_ovf.reserve((size_t)s->slots * chunk_subj * 8 + 8));
     TRY(s->d_counters.reserve(256));
-    if (db->n_groups > 0)
-        TRY(s->d_scr_inter.reserve((size_t)s->L.grid_inter * W * db->max_rows * 512));
+    s->scr_rows = s->g_cut > 0 ? db->grp_rows[s->g_cut - 1] : 0;
+    if (s->g_cut > 0)
+        TRY(s->d_scr_inter.reserve((size_t)s->L.grid_inter * W * s->scr_rows * 512));
     const int64_t islots = std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
     const size_t items_bytes =
@@ -919,11 +985,11 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     const bool long_pos = s->has_long && s->position == s->n_chunks;
     Items it;
     if (long_pos) {
-        build_items(db, s->plan, slots, mpad, qlen, 0, 0, true, 1, it);
+        build_items(db, s->plan, slots, mpad, qlen, 0, 0, true, s->long_ids, 1, it);
     } else {
         const int64_t b0 = s->position * s->chunk_blocks;
         const int64_t b1 = std::min(s->blocks, b0 + s->chunk_blocks);
-        build_items(db, s->plan, slots, mpad, qlen, b0, b1, false, 1, it);
+        build_items(db, s->plan, slots, mpad, qlen, b0, b1, false, s->long_ids, 1, it);
     }
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     int32_t *hi = s->h_items.as<int32_t>();
@@ -952,6 +1018,7 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.ovf_cap = cap;
     pb.counters = s->d_counters.as<int32_t>();
     pb.scr_inter = s->d_scr_inter.as<uint32_t>();
+    pb.scr_rows = s->scr_rows;
     pb.scr_intra = s->d_scr_intra.as<int32_t>();
     Launch L = s->L;
     L.grid_inter = (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
@@ -1148,19 +1215,12 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
     const int64_t simds = 4LL * db->cus;
     int64_t cut;   // subjects longer than cut go to the long list
     const int32_t lt = opts ? opts->long_threshold : 0;
+    db->fixed_cut = lt != 0;
     if (lt == -1) cut = INT64_MAX;
     else if (lt == 1) cut = -1;
     else if (lt > 1) cut = lt;
-    else {
-        // Too few subjects to give every SIMD a wavefront: all wave-per-pair.
-        if (n_seqs < simds * kGroup) cut = -1;
-        else {
-            // The longest lane-per-subject group may hold its SIMD for at most half
-            // the average per-SIMD share of rows.
-            const double share = (double)total / kGroup / simds;
-            cut = std::max<int64_t>(1024, (int64_t)(0.5 * share));
-        }
-    }
+    else if (n_seqs < simds * kGroup) cut = -1;   // cannot give every SIMD a wavefront
+    else cut = kGroupMaxLen;   // each search routes its own cut below this (route_cut)
     int64_t n_short = 0;
     while (n_short < n_seqs && db->len[order[n_short]] <= cut) ++n_short;
     db->long_threshold = cut;
@@ -1184,6 +1244,7 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
         codes_total += rows * kWave;
         db->max_rows = std::max<int32_t>(db->max_rows, (int32_t)rows);
         db->inter_padded_rows += rows * kGroup;
+        db->grp_res_prefix.push_back(db->inter_res);
         for (int x = 0; x < kGroup; ++x) {
             const int64_t si = (int64_t)g * kGroup + x;
             if (si < n_short) {
@@ -1192,6 +1253,7 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
             }
         }
     }
+    db->grp_res_prefix.push_back(db->inter_res);
     std::vector<uint16_t> codes((size_t)codes_total);
     {
         const int nth = (int)std::max(1, std::min(16, ng / 64));
@@ -1236,6 +1298,7 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
         HIPX(hipMemcpy(db->d_grp_rows.p, db->grp_rows.data(), (size_t)ng * 4, hipMemcpyHostToDevice));
         HIPX(hipMemcpy(db->d_grp_ids.p, gids.data(), gids.size() * 4, hipMemcpyHostToDevice));
     }
+    db->grp_ids = std::move(gids);
     *out = db.release();
     return SW_OK;
 }

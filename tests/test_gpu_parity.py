@@ -273,3 +273,28 @@ def test_plain_small_workload(swmi, orc):
         expect_equal(ti, ei, "plain_small topk idx")
     finally:
         db.close()
+
+
+def test_auto_routing_large_database(swmi, orc):
+    """A database big enough for the lane-per-subject kernel with a long tail:
+    the per-search cut routes the longest groups to the wave-per-pair kernel
+    for one query and keeps them lane-per-subject for a batch."""
+    rng = np.random.Generator(np.random.PCG64(91))
+    n = 140_000
+    lens = sd.lognormal_lengths(rng, n, 40, 1, 3000)
+    lens[rng.choice(n, 300, replace=False)] = rng.integers(1100, 3000, size=300)
+    res, off = sd.pack_sequences([rng.integers(0, 20, size=int(L)).astype(np.uint8) for L in lens])
+    M = sd.blosum_style_matrix()
+    db = swmi.Database(res, off, 20)
+    try:
+        q = sd.random_residues(rng, 70)
+        exp = orc.search(q, res, off, M, 2, 12)
+        expect_equal(db.search(q, M, 2, 12), exp, "auto routing single query")
+        st = db.stats()
+        assert st["intra_pairs"] > 0 and st["inter_cells"] > 0
+        qs = [sd.random_residues(rng, int(L)) for L in (40, 300, 129)]
+        ts, ti, al = db.search_batch(qs, M, 2, 12, 10, all_scores=True)
+        for x, qq in enumerate(qs):
+            expect_equal(al[x], orc.search(qq, res, off, M, 2, 12), f"auto routing batch q{x}")
+    finally:
+        db.close()
