@@ -156,14 +156,23 @@ int qlen_bucket(int64_t qlen) {
 // Work item lists of one device pass, built on the host.
 struct Items {
     std::vector<int32_t> inter_q, inter_g;   // lane-per-subject: (slot, first group of block)
-    std::vector<int32_t> intra_q, intra_ids; // wave-per-pair: (slot, kIntraWaves subject ids)
+    std::vector<int32_t> intra_q, intra_ids; // wave-per-pair: (slot, per_item subject ids)
+    int per_item = kIntraWaves;              // subjects per wave-per-pair item
 };
+
+// Subjects per wave of the wave-per-pair kernel: two packed fp16 halves when
+// there are enough pairs to keep every SIMD busy with half as many waves,
+// one exact int32 alignment otherwise (and in the int16 plan).
+int intra_per_wave(const Plan &plan, int64_t pairs, int cus) {
+    return plan.tier == TIER_F16X2 && pairs >= 32LL * cus ? 2 : 1;
+}
 
 // Kernels and grids of one pass.
 struct Launch {
     Plan plan;
     int Ti = 16;
     int grid_inter = 0, grid_long = 0, grid_ovf = 0;
+    bool packed_long = false;   // wave-per-pair items hold two subjects per wave
 };
 
 }  // namespace
@@ -333,21 +342,23 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     it.intra_ids.clear();
     if (!with_long) return;
     const int64_t nlong = (int64_t)long_ids.size();
-    const int64_t nlblk = (nlong + kIntraWaves - 1) / kIntraWaves;
+    const int per = kIntraWaves * intra_per_wave(plan, nlong * (int64_t)slots.size(), db->cus);
+    it.per_item = per;
+    const int64_t nlblk = (nlong + per - 1) / per;
     std::vector<std::pair<int64_t, std::pair<int32_t, int64_t>>> u;
     for (size_t x = 0; x < slots.size(); ++x)
         for (int64_t bk = 0; bk < nlblk; ++bk) {
             if (stride > 1 && (bk % stride) != 0) continue;
-            u.push_back({db->len[long_ids[bk * kIntraWaves]] * qlen[x], {slots[x], bk}});
+            u.push_back({db->len[long_ids[bk * per]] * qlen[x], {slots[x], bk}});
         }
     std::stable_sort(u.begin(), u.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
     it.intra_q.resize(u.size());
-    it.intra_ids.resize(u.size() * kIntraWaves);
+    it.intra_ids.resize(u.size() * per);
     for (size_t i = 0; i < u.size(); ++i) {
         it.intra_q[i] = u[i].second.first;
-        for (int w = 0; w < kIntraWaves; ++w) {
-            const int64_t x = u[i].second.second * kIntraWaves + w;
-            it.intra_ids[i * kIntraWaves + w] = x < nlong ? long_ids[x] : -1;
+        for (int w = 0; w < per; ++w) {
+            const int64_t x = u[i].second.second * per + w;
+            it.intra_ids[i * per + w] = x < nlong ? long_ids[x] : -1;
         }
     }
 }
@@ -424,15 +435,22 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
     ia.max_len_pad = intra_scratch_rows(db);
     ia.scores = b.scores;
     ia.n_seqs = db->n_seqs;
+    ia.thr = L.plan.thr;
+    ia.ovf_q = b.ovf_q;
+    ia.ovf_id = b.ovf_id;
+    ia.ovf_count = b.counters + 1;
+    ia.ovf_cap = b.ovf_cap;
+    const bool packed_long = L.packed_long;
     if (b.n_intra > 0) {
         IntraArgs la = ia;
         la.item_q = b.il_q;
         la.item_ids = b.il_ids;
         la.n_items = (int32_t)b.n_intra;
         la.counter = b.counters + 2;
-        HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
+        if (packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_long, st));
+        else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
     }
-    if (b.n_inter > 0) {
+    if (b.n_inter > 0 || (packed_long && b.n_intra > 0)) {
         IntraArgs oa = ia;
         oa.item_q = b.ovf_q;
         oa.item_ids = b.ovf_id;
@@ -476,7 +494,7 @@ StageLayout stage_layout(int32_t nq, int64_t prof_bytes, const Items &it) {
     s.gap = o;
     o += (size_t)round_up((int64_t)nq * 8, 256);
     s.items = o;
-    o += (size_t)round_up((int64_t)(it.inter_q.size() * 2 + it.intra_q.size() * (1 + kIntraWaves)) * 4, 256);
+    o += (size_t)round_up((int64_t)(it.inter_q.size() * 2 + it.intra_q.size() * (1 + it.per_item)) * 4, 256);
     s.prof = o;
     o += (size_t)round_up(prof_bytes, 256);
     s.total = o;
@@ -527,7 +545,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     build_items(db, plan, slots, mpad, qlen, 0, nblk, true, long_ids, item_stride, it);
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     if (n_inter > INT32_MAX || n_intra > INT32_MAX) return fail(SW_EINVAL, "batch too large");
-    const Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra);
+    Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra);
+    L.packed_long = it.per_item == 2 * kIntraWaves;
     const int32_t rows_alloc = g_cut > 0 ? db->grp_rows[g_cut - 1] : 0;
     int64_t long_res = 0;
     for (int32_t id : long_ids) long_res += db->len[id];
@@ -570,7 +589,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
         std::memcpy(p, it.inter_q.data(), n_inter * 4);
         std::memcpy(p + n_inter, it.inter_g.data(), n_inter * 4);
         std::memcpy(p + 2 * n_inter, it.intra_q.data(), n_intra * 4);
-        std::memcpy(p + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * kIntraWaves * 4);
+        std::memcpy(p + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * it.per_item * 4);
     }
     HIPX(hipMemcpyAsync(ds, hs, sl.total, hipMemcpyHostToDevice, st));
 
@@ -836,6 +855,7 @@ struct sw_server {
     Plan plan;
     int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
     int64_t g_cut = 0;
+    int64_t ovf_cap = 0;
     int32_t scr_rows = 0;
     std::vector<int32_t> long_ids;   // wave-per-pair subjects, longest first
     bool has_long = false;
@@ -891,7 +911,8 @@ int server_setup(sw_server *s) {
     const int64_t n = db->n_seqs;
     // the largest pass: every slot against one chunk, or against the long list
     const int64_t inter_items = (int64_t)s->slots * s->chunk_blocks;
-    const int64_t nlblk = ((int64_t)s->long_ids.size() + kIntraWaves - 1) / kIntraWaves;
+    const int per = kIntraWaves;   // the int32 layout has the most items
+    const int64_t nlblk = ((int64_t)s->long_ids.size() + per - 1) / per;
     const int64_t intra_items = (int64_t)s->slots * nlblk;
     s->L = launch_config(db, s->plan, 1 << 14, std::max<int64_t>(inter_items, 1),
                          std::max<int64_t>(intra_items, 1));
@@ -899,8 +920,9 @@ int server_setup(sw_server *s) {
     TRY(s->h_meta.reserve((size_t)s->slots * 24 + 256));
     std::memset(s->h_meta.p, 0, (size_t)s->slots * 24 + 256);
     TRY(s->d_scores.reserve((size_t)s->slots * n * 4 + 4));
-    const int64_t chunk_subj = s->chunk_blocks * W * kGroup;
-    TRY(s->d_ovf.reserve((size_t)s->slots * chunk_subj * 8 + 8));
+    const int64_t chunk_subj = std::max<int64_t>(s->chunk_blocks * W * kGroup, (int64_t)s->long_ids.size());
+    s->ovf_cap = (int64_t)s->slots * chunk_subj;
+    TRY(s->d_ovf.reserve((size_t)s->ovf_cap * 8 + 8));
     TRY(s->d_counters.reserve(256));
     s->scr_rows = s->g_cut > 0 ? db->grp_rows[s->g_cut - 1] : 0;
     if (s->g_cut > 0)
@@ -908,7 +930,7 @@ int server_setup(sw_server *s) {
     const int64_t islots = std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
     const size_t items_bytes =
-        (size_t)(std::max(inter_items * 2, intra_items * (1 + kIntraWaves)) + 64) * 4;
+        (size_t)(std::max(inter_items * 2, intra_items * (1 + per)) + 64) * 4;
     TRY(s->d_items.reserve(items_bytes));
     TRY(s->h_items.reserve(items_bytes));
     TRY(s->d_topk.reserve(topk_work_bytes(s->slots, SW_MAX_K)));
@@ -996,8 +1018,8 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     std::memcpy(hi, it.inter_q.data(), n_inter * 4);
     std::memcpy(hi + n_inter, it.inter_g.data(), n_inter * 4);
     std::memcpy(hi + 2 * n_inter, it.intra_q.data(), n_intra * 4);
-    std::memcpy(hi + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * kIntraWaves * 4);
-    const size_t ib = (size_t)(2 * n_inter + n_intra * (1 + kIntraWaves)) * 4;
+    std::memcpy(hi + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * it.per_item * 4);
+    const size_t ib = (size_t)(2 * n_inter + n_intra * (1 + it.per_item)) * 4;
     if (ib) HIPX(hipMemcpyAsync(s->d_items.p, hi, ib, hipMemcpyHostToDevice, st));
     PassBufs pb;
     uint8_t *dm = s->d_meta.as<uint8_t>();
@@ -1012,7 +1034,7 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.n_inter = n_inter;
     pb.n_intra = n_intra;
     pb.scores = s->d_scores.as<int32_t>();
-    const int64_t cap = (int64_t)s->slots * s->chunk_blocks * s->plan.waves * kGroup;
+    const int64_t cap = s->ovf_cap;
     pb.ovf_q = s->d_ovf.as<int32_t>();
     pb.ovf_id = pb.ovf_q + cap;
     pb.ovf_cap = cap;
@@ -1021,6 +1043,7 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.scr_rows = s->scr_rows;
     pb.scr_intra = s->d_scr_intra.as<int32_t>();
     Launch L = s->L;
+    L.packed_long = it.per_item == 2 * kIntraWaves;
     L.grid_inter = (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
     L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
     TRY(enqueue_pass(db, L, pb, st));

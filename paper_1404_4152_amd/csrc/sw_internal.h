@@ -70,6 +70,10 @@ struct IntraArgs {
     int64_t max_len_pad;     // rows per scratch slot (>= longest subject rounded to 64, + 128)
     int32_t *scores;
     int64_t n_seqs;
+    // packed-fp16 variant only: flagged pairs go to the exact recompute list
+    int32_t thr;
+    int32_t *ovf_q, *ovf_id, *ovf_count;
+    int64_t ovf_cap;
 };
 
 // Raise the dynamic-LDS limit of every kernel variant (once per device, before
@@ -84,6 +88,9 @@ int inter_max_grid(int R, int strip, int waves);      // resident workgroups tha
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);
+// Packed-fp16 wave-per-pair kernel: each wave aligns one query with two
+// subjects (item_ids holds 2 * waves ids per item).
+hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 

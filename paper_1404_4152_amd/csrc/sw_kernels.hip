@@ -527,6 +527,188 @@ __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
 
 int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 
+// ---------------------------------------------------------------------------
+// Packed-fp16 wave-per-pair kernel: the systolic schedule above with one
+// subject in each 16-bit half of every lane (same query), so one instruction
+// advances two alignments.  The two halves read their substitution scores from
+// two profile rows; one v_perm per column pair packs them.  Exactness as in the
+// lane-per-subject f16x2 tier: a half whose best reaches thr is flagged and
+// recomputed in int32.
+// ---------------------------------------------------------------------------
+template <int T>
+__device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
+                                           const uint2 *pb, const Lane<TIER_F16X2> &ops,
+                                           uint32_t hb_prev, uint32_t fin, h2 &best,
+                                           uint32_t &hout, uint32_t &fout) {
+    h2 hdiag = as_v<h2>(hb_prev);
+    h2 f = as_v<h2>(fin);
+#pragma unroll
+    for (int j4 = 0; j4 < T / 4; ++j4) {
+        const uint2 A = pa[j4], B = pb[j4];
+        // (low half from subject a's row, high half from subject b's row)
+        const uint32_t sv[4] = {__builtin_amdgcn_perm(B.x, A.x, 0x05040100u),
+                                __builtin_amdgcn_perm(B.x, A.x, 0x07060302u),
+                                __builtin_amdgcn_perm(B.y, A.y, 0x05040100u),
+                                __builtin_amdgcn_perm(B.y, A.y, 0x07060302u)};
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+            const int j = j4 * 4 + u;
+            h2 h0, h1;
+            {
+                const h2 hold = H[j];
+                h0 = ops.hmax(ops.diag(hdiag, as_v<h2>(sv[u])), E[j], f);
+                const h2 t = ops.open(h0);
+                E[j] = ops.gap(E[j], t);
+                f = ops.gap(f, t);
+                H[j] = h0;
+                hdiag = hold;
+            }
+            {
+                const h2 hold = H[j + 1];
+                h1 = ops.hmax(ops.diag(hdiag, as_v<h2>(sv[u + 1])), E[j + 1], f);
+                const h2 t = ops.open(h1);
+                E[j + 1] = ops.gap(E[j + 1], t);
+                f = ops.gap(f, t);
+                H[j + 1] = h1;
+                hdiag = hold;
+            }
+            best = ops.best2(best, h0, h1);
+        }
+    }
+    hout = as_u(H[T - 1]);
+    fout = as_u(f);
+}
+
+template <int T, int W>
+__global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
+    typedef Lane<TIER_F16X2> L;
+    constexpr int PW = 64 * T;          // query columns per pass
+    constexpr int RS = PW + 8;          // fp16 entries per profile row (padded)
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    uint16_t *prof = (uint16_t *)lds;
+    __shared__ int s_item;
+
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int pad = a.R - 1;
+    int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
+    const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int q = a.item_q[it];
+        const int id_a = a.item_ids[(size_t)it * 2 * W + 2 * w];
+        const int id_b = a.item_ids[(size_t)it * 2 * W + 2 * w + 1];
+        const int na = id_a >= 0 ? (int)(a.off[id_a + 1] - a.off[id_a]) : 0;
+        const int nb = id_b >= 0 ? (int)(a.off[id_b + 1] - a.off[id_b]) : 0;
+        const int n = na > nb ? na : nb;
+        const uint8_t *sa = id_a >= 0 ? a.res + a.off[id_a] : a.res;
+        const uint8_t *sb = id_b >= 0 ? a.res + a.off[id_b] : a.res;
+        const int mp = a.qs.mpad[q];
+        const int npass = (a.qs.qlen[q] + PW - 1) / PW;
+        const int8_t *qp = a.qs.qp[q];
+        constexpr int kCap = 2048;
+        const L ops(min(a.qs.gap[2 * q], kCap), min(a.qs.gap[2 * q + 1], kCap));
+        h2 best = L::zero();
+
+        for (int p = 0; p < npass; ++p) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
+                const int r = e / PW, c = e - r * PW;
+                const int col = p * PW + c;
+                prof[r * RS + c] = L::enc(col < mp ? (int)qp[(size_t)r * mp + col] : 0);
+            }
+            __syncthreads();
+            if (n <= 0) continue;
+
+            const bool has_in = p > 0, has_out = p + 1 < npass;
+            const int nblk = (n + 63) / 64;
+            const int steps = has_out ? nblk * 64 + 63 : n + 63;
+            h2 H[T], E[T];
+#pragma unroll
+            for (int j = 0; j < T; ++j) { H[j] = L::zero(); E[j] = L::zero(); }
+            uint32_t hb_prev = 0, hout = 0, fout = 0;
+            int r = pad | (pad << 8);   // residue codes of both subjects, a in the low byte
+            int cH = 0, cF = 0;
+            auto feed = [&](int row, int &fr, int &fh, int &ff) {
+                const int ra = row < na ? sa[row] : pad;
+                const int rb = row < nb ? sb[row] : pad;
+                fr = ra | (rb << 8);
+                fh = (has_in && row < n) ? wsc[2 * row] : 0;
+                ff = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+            };
+            int fR, fH, fF, nR, nH, nF;
+            feed(lane, fR, fH, fF);
+            feed(64 + lane, nR, nH, nF);
+            for (int t = 0; t < steps; ++t) {
+                if (t > 0 && (t & 63) == 0) {
+                    fR = nR; fH = nH; fF = nF;
+                    feed(t + 64 + lane, nR, nH, nF);
+                }
+                r = shr1(fR, r);
+                const int hin = shr1(fH, (int)hout);
+                const int fin = shr1(fF, (int)fout);
+                fR = shl1(fR, fR);
+                fH = shl1(fH, fH);
+                fF = shl1(fF, fF);
+                const uint2 *pa = (const uint2 *)(prof + (r & 0xff) * RS + lane * T);
+                const uint2 *pb = (const uint2 *)(prof + (r >> 8) * RS + lane * T);
+                intra2_row<T>(H, E, pa, pb, ops, hb_prev, (uint32_t)fin, best, hout, fout);
+                hb_prev = (uint32_t)hin;
+                if (has_out) {
+                    cH = shl1((int)hout, cH);
+                    cF = shl1((int)fout, cF);
+                    if ((t & 63) == 62 && t >= 126) {
+                        const int row = t - 126 + lane;
+                        wsc[2 * row] = cH;
+                        wsc[2 * row + 1] = cF;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const h2 other = as_v<h2>((uint32_t)__shfl_xor((int)as_u(best), o, 64));
+            best = __builtin_elementwise_maximum(best, other);
+        }
+        if (lane == 0) {
+            const int ids[2] = {id_a, id_b};
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                if (ids[half] < 0) continue;
+                bool flag;
+                const int v = L::value(best, half, a.thr, &flag);
+                a.scores[(size_t)q * a.n_seqs + ids[half]] = v;
+                if (flag) {
+                    const int pos = atomicAdd(a.ovf_count, 1);
+                    if (pos < a.ovf_cap) {
+                        a.ovf_q[pos] = q;
+                        a.ovf_id[pos] = ids[half];
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int T, int W>
+static hipError_t launch_intra2_t(const IntraArgs &a, int grid, hipStream_t st) {
+    const int lds = intra_lds_bytes(a.R, T);
+    hipLaunchKernelGGL((intra2_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStream_t st) {
+    if (waves != 4) return hipErrorInvalidValue;
+    if (T == 4) return launch_intra2_t<4, 4>(a, grid, st);
+    if (T == 8) return launch_intra2_t<8, 4>(a, grid, st);
+    if (T == 16) return launch_intra2_t<16, 4>(a, grid, st);
+    return hipErrorInvalidValue;
+}
+
 template <int T, int W>
 static hipError_t launch_intra_t(const IntraArgs &a, int grid, hipStream_t st) {
     const int lds = intra_lds_bytes(a.R, T);
@@ -758,6 +940,8 @@ hipError_t prepare_kernels() {
         (const void *)intra_kernel<4, 1>,  (const void *)intra_kernel<8, 1>,
         (const void *)intra_kernel<16, 1>, (const void *)intra_kernel<4, 4>,
         (const void *)intra_kernel<8, 4>,  (const void *)intra_kernel<16, 4>,
+        (const void *)intra2_kernel<4, 4>, (const void *)intra2_kernel<8, 4>,
+        (const void *)intra2_kernel<16, 4>,
     };
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -115,18 +115,21 @@ def test_asymmetric_matrix_orientation(swmi, orc):
             db.close()
 
 
-@pytest.mark.parametrize("tier", [1, 2])
-def test_forced_overflow_recompute(swmi, orc, tier):
-    """A lowered threshold flags many lanes; the int32 recompute keeps every score exact."""
+@pytest.mark.parametrize("tier,route", [(1, -1), (2, -1), (1, 1)])
+def test_forced_overflow_recompute(swmi, orc, tier, route):
+    """A lowered threshold flags many lanes (lane-per-subject kernel) or halves
+    (packed wave-per-pair kernel); the int32 recompute keeps every score exact."""
     rng = np.random.Generator(np.random.PCG64(31 + tier))
     M = sd.blosum_style_matrix()
-    res, off = random_db(rng, 1500, 20, 1, 300, zero_every=41)
-    db = swmi.Database(res, off, 20, long_threshold=-1)
+    # enough pairs for the packed wave-per-pair kernel when route == 1
+    res, off = (random_db(rng, 1500, 20, 1, 300, zero_every=41) if route == -1
+                else random_db(rng, 9000, 20, 1, 120, zero_every=41))
+    db = swmi.Database(res, off, 20, long_threshold=route)
     try:
         db.set_opts(tier=tier, sat_threshold=20)
         for L in [33, 250, 700]:
             q = sd.random_residues(rng, L)
-            print(f"forced overflow tier={tier} qlen={L}", flush=True)
+            print(f"forced overflow tier={tier} route={route} qlen={L}", flush=True)
             exp = orc.search(q, res, off, M, 2, 12)
             expect_equal(db.search(q, M, 2, 12), exp, f"forced overflow L={L}")
             st = db.stats()
@@ -144,7 +147,8 @@ def test_planted_homologs_exceed_narrow_tiers(swmi, orc):
     q_long = sd.random_residues(rng, 900)
     q_long[::2] = 17        # self score > 32767
     q_mid = sd.random_residues(rng, 500)
-    res, off = random_db(rng, 600, A, 1, 400)
+    # 9,000 subjects: enough pairs for the packed wave-per-pair kernel (route 1)
+    res, off = random_db(rng, 9000, A, 1, 120)
     res, off = sd.plant_homologs(res, off, [q_long, q_mid, q_long],
                                  where=[10, 200, 599], identity=0.9)
     assert orc.sw_score(q_long, res[off[10]:off[11]], M, 2, 12) > 32767
