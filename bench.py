@@ -104,6 +104,11 @@ def run_plain(args, swmi, sd, torch):
     overridden = bool(args.tier or args.strip or args.waves)
     if overridden:
         db.set_opts(tier=args.tier, strip=args.strip, waves=args.waves)
+    elif not args.no_autotune:
+        # plan per query-length bucket, timed on a sample of this database
+        t0 = time.perf_counter()
+        swmi.sw_db_autotune(db.h, M, w.alpha, w.beta, [len(q) for q in queries], None)
+        log(f"[bench] autotuned plans in {time.perf_counter() - t0:.1f}s")
     # kernels, HIP events and torch's synchronisation share torch's current stream
     sptr = torch.cuda.current_stream().cuda_stream
     sum_q = sum(len(q) for q in queries)
@@ -140,8 +145,10 @@ def run_plain(args, swmi, sd, torch):
         "data": "synthetic",
         "config": {"workload": w.name, "subjects": len(off) - 1, "residues": int(len(res)),
                    "queries": len(queries), "sum_query_len": sum_q, "k": args.k,
-                   "alpha": w.alpha, "beta": w.beta, "tier": st0["tier"], "strip": st0["strip"],
-                   "waves": st0["waves"], "parallelism": "single GPU"},
+                   "alpha": w.alpha, "beta": w.beta,
+                   "plans": sorted({(s["tier"], s["strip"], s["waves"]) for s in all_sts}),
+                   "autotuned": not overridden and not args.no_autotune,
+                   "parallelism": "single GPU"},
         "frac_of_f16x2_peak_gcups": round(gcups / PEAK_GCUPS_F16X2, 4),
         "kernel_gcups": round(cells_step * args.steps /
                               (sum(s["kernel_ms"] for s in all_sts) / 1e3) / 1e9, 2),
@@ -271,6 +278,7 @@ def main():
     ap.add_argument("--tier", type=int, default=0)
     ap.add_argument("--strip", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true")

@@ -711,8 +711,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
 // ---------------------------------------------------------------------------
 const Plan kCandidates[] = {
     {TIER_F16X2, 32, 4, 0}, {TIER_F16X2, 64, 4, 0}, {TIER_F16X2, 32, 8, 0},
-    {TIER_F16X2, 16, 8, 0}, {TIER_F16X2, 16, 4, 0}, {TIER_I16X2, 32, 4, 0},
-    {TIER_I16X2, 64, 4, 0}, {TIER_I16X2, 32, 8, 0},
+    {TIER_I16X2, 32, 4, 0}, {TIER_I16X2, 64, 4, 0}, {TIER_F16X2, 16, 8, 0},
 };
 
 bool read_cache(sw_db *db, const char *path) {
@@ -770,8 +769,11 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
     if (db->n_groups == 0) return SW_OK;   // nothing runs lane-per-subject
     const sw_search_opts saved = db->opts;
     std::map<int, double> best_gcups;
-    // every stride-th block only, so a candidate costs a fraction of a search
-    const int64_t stride = std::max<int64_t>(1, std::min<int64_t>(8, db->n_groups / 2048));
+    // Time every stride-th block only, but keep at least 16 items per resident
+    // workgroup: with fewer, the tail of the work queue, not the plan, decides.
+    const int64_t resident = inter_max_grid(db->R, 32, 4);
+    const int64_t stride =
+        std::max<int64_t>(1, std::min<int64_t>(8, (db->n_groups / 4) / (16 * resident)));
     uint32_t lcg = 12345u;
     for (int32_t x = 0; x < n_qlens; ++x) {
         const int64_t L = std::max(1, std::min(qlens[x], SW_MAX_LEN));
@@ -793,14 +795,14 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
             o.waves = cand.waves;
             db->opts = o;
             double ms = 1e30;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches and buffers
                 int rc = run_search(db, 1, q.data(), off, sc, 0, nullptr, nullptr, nullptr, nullptr,
                                     nullptr, stride);
                 if (rc != SW_OK) {
                     db->opts = saved;
                     return rc;
                 }
-                ms = std::min(ms, db->last.inter_ms);
+                if (rep > 0) ms = db->last.inter_ms;
             }
             const double gc = (double)db->last.inter_cells / stride / (ms * 1e6);
             if (gc > best) {
