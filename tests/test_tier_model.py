@@ -146,6 +146,9 @@ def test_model_rejects_an_invalid_fp16_threshold(orc):
     M = np.full((A, A), -3, np.int8)
     np.fill_diagonal(M, 127)
     rng = np.random.Generator(np.random.PCG64(3))
-    Q = rng.integers(0, A, size=(48, 40)).astype(np.uint8)
+    base = rng.integers(0, A, size=(48, 40)).astype(np.uint8)
+    Q = base.copy()
+    S = base.copy()
+    S[::3, ::5] = (S[::3, ::5] + 1) % A      # odd scores between 2048 and 4000 round in fp16
     with pytest.raises(AssertionError):
-        check_claim(orc, Q, Q.copy(), M, 2, 12, 4000, "f16")
+        check_claim(orc, Q, S, M, 2, 12, 4000, "f16")
