@@ -149,6 +149,7 @@ def test_model_rejects_an_invalid_fp16_threshold(orc):
     base = rng.integers(0, A, size=(48, 40)).astype(np.uint8)
     Q = base.copy()
     S = base.copy()
-    S[::3, ::5] = (S[::3, ::5] + 1) % A      # odd scores between 2048 and 4000 round in fp16
+    S[::3, ::5] = (S[::3, ::5] + 1) % A
+    Q[1::4, :25] = rng.integers(0, A, size=(12, 25))   # scores between 2048 and 4000 round in fp16
     with pytest.raises(AssertionError):
         check_claim(orc, Q, S, M, 2, 12, 4000, "f16")
