@@ -97,6 +97,14 @@ def lib():
     """The loaded libswmi.so; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: PyTorch ships its own libamdhip64.so.7, and
+        # the library's streams and device pointers must live in the same
+        # runtime as the caller's tensors and streams.  Loading torch first makes
+        # libswmi bind to that runtime instead of a second copy from /opt/rocm.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                               "or python paper_1404_4152_amd/build.py")

@@ -302,3 +302,58 @@ def test_auto_routing_large_database(swmi, orc):
             expect_equal(al[x], orc.search(qq, res, off, M, 2, 12), f"auto routing batch q{x}")
     finally:
         db.close()
+
+
+def test_device_output_on_caller_stream(swmi, orc):
+    """sw_db_search_dev writes into caller device memory (a torch tensor) on the
+    caller's stream; sw_db_topk on the same stream agrees."""
+    import torch
+    torch.cuda.set_device(0)
+    rng = np.random.Generator(np.random.PCG64(93))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 1200, 20, 0, 300, zero_every=31)
+    db = swmi.Database(res, off, 20, long_threshold=-1)
+    try:
+        s = torch.cuda.Stream()
+        out = torch.full((len(off) - 1,), -7, dtype=torch.int32, device="cuda")
+        q = sd.random_residues(rng, 211)
+        with torch.cuda.stream(s):
+            swmi.sw_db_search_dev(db.h, q, M, 2, 12, out.data_ptr(), stream=s.cuda_stream)
+            ts, ti = swmi.sw_db_topk(db.h, q, M, 2, 12, 5, stream=s.cuda_stream)
+        s.synchronize()
+        exp = orc.search(q, res, off, M, 2, 12)
+        expect_equal(out.cpu().numpy(), exp, "device output")
+        es, ei = oracle.topk(exp, 5)
+        expect_equal(ts, es, "topk on caller stream")
+        expect_equal(ti, ei, "topk idx on caller stream")
+    finally:
+        db.close()
+
+
+def test_topk_maximum_k(swmi, orc):
+    """k = SW_MAX_K (4096) over a database with heavy ties, and k above n."""
+    rng = np.random.Generator(np.random.PCG64(95))
+    A = 3
+    M = np.array([[3, -2, -2], [-2, 3, -2], [-2, -2, 3]], np.int8)
+    res, off = random_db(rng, 6000, A, 0, 20)
+    q = sd.uniform_residues(rng, 15, A)
+    db = swmi.Database(res, off, A, long_threshold=-1)
+    try:
+        exp = orc.search(q, res, off, M, 1, 3)
+        ts, ti = db.topk(q, M, 1, 3, swmi.SW_MAX_K)
+        es, ei = oracle.topk(exp, swmi.SW_MAX_K)
+        expect_equal(ts, es, "k=4096 scores")
+        expect_equal(ti, ei, "k=4096 indices")
+        with pytest.raises(swmi.SwError):
+            db.topk(q, M, 1, 3, swmi.SW_MAX_K + 1)
+    finally:
+        db.close()
+    res2, off2 = random_db(rng, 50, A, 1, 20)
+    db = swmi.Database(res2, off2, A)
+    try:
+        ts, ti = db.topk(q, M, 1, 3, 4000)
+        es, ei = oracle.topk(orc.search(q, res2, off2, M, 1, 3), 4000)
+        expect_equal(ts, es, "k > n scores")
+        expect_equal(ti, ei, "k > n indices")
+    finally:
+        db.close()
