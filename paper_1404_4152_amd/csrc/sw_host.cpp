@@ -241,10 +241,14 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t qlen) {
     return SW_OK;
 }
 
-Plan plan_for(const sw_db *db, int64_t max_qlen) {
+// alpha: the gap extension of the search (0 when it varies per query).
+Plan plan_for(const sw_db *db, int64_t max_qlen, int alpha) {
     Plan p;
     auto it = db->tuned.find(qlen_bucket(max_qlen));
     if (it != db->tuned.end()) p = it->second;
+    // The fp16 tier's ceiling falls by 33 per unit of alpha (row frame);
+    // past kFrameMaxAlpha the int16 tier flags far fewer lanes.
+    if (p.tier == TIER_F16X2 && alpha > kFrameMaxAlpha) p.tier = TIER_I16X2;
     if (db->opts.tier) p.tier = db->opts.tier;
     if (db->opts.strip) p.strip = db->opts.strip;
     if (db->opts.waves) p.waves = db->opts.waves;
@@ -532,7 +536,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     if ((int64_t)nq * db->n_seqs > ((int64_t)1 << 40)) return fail(SW_EINVAL, "batch too large");
     HIPX(hipSetDevice(db->device));
     hipStream_t st = user_stream ? user_stream : db->stream;
-    const Plan plan = plan_for(db, max_qlen);
+    const Plan plan = plan_for(db, max_qlen, sc->alpha);
     const int64_t n = db->n_seqs;
 
     std::vector<int32_t> slots(nq);
@@ -888,7 +892,7 @@ namespace {
 int server_setup(sw_server *s) {
     sw_db *db = s->db;
     HIPX(hipSetDevice(db->device));
-    s->plan = plan_for(db, 512);
+    s->plan = plan_for(db, 512, 0);
     const int W = s->plan.waves;
     {
         // route as if half the slots held 400-residue queries

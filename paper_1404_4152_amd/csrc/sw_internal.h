@@ -22,6 +22,19 @@ constexpr int kQPad = 64;
 // Exactness ceilings of the narrow tiers (see sw_kernels.hip for the proofs).
 constexpr int kThrF16 = 1920;    // fp16 holds every integer in [-2048, 2048]
 constexpr int kThrI16 = 32767;   // saturating int16
+// The lane-per-subject fp16 tier keeps values offset by up to kFrameRows *
+// alpha (row frame, see sw_kernels.hip), so its ceiling for a query with gap
+// extension alpha is kThrF16 - (kFrameRows + 1) * alpha.  Above
+// kFrameMaxAlpha the planner prefers the int16 tier; above kFrameFlagAlpha
+// the fp16 tier flags every lane of the query for the exact recompute.
+constexpr int kFrameRows = 32;
+constexpr int kFrameMaxAlpha = 28;
+constexpr int kFrameFlagAlpha = 56;
+__host__ __device__ inline int frame_thr(int thr, int alpha) {
+    if (alpha > kFrameFlagAlpha) return 0;
+    const int c = kThrF16 - (kFrameRows + 1) * alpha;
+    return thr < c ? thr : c;
+}
 
 enum Tier : int { TIER_F16X2 = 1, TIER_I16X2 = 2 };
 
@@ -47,7 +60,7 @@ struct InterArgs {
     int32_t *counter;        // work-queue head, zero before launch
     QuerySet qs;
     int32_t R;
-    int32_t thr;             // a lane whose best reaches thr is flagged
+    int32_t thr;             // a lane whose best reaches thr is flagged (fp16: see frame_thr)
     uint32_t *scratch;       // boundary columns: per (slot, wave) max_rows * 64 * 2 dwords
     int32_t max_rows;
     int32_t *scores;         // [query][n_seqs], caller order

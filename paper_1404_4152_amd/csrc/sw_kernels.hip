@@ -5,13 +5,15 @@
 //   H(i,j) = max{0, H(i-1,j-1) + M, E(i,j), F(i,j)}
 //   E(i,j) = max{E(i-1,j) - alpha, H(i-1,j) - beta}
 //   F(i,j) = max{F(i,j-1) - alpha, H(i,j-1) - beta}
-// Every kernel evaluates it in the same per-cell form:
+// The int32 and int16 paths evaluate it in the per-cell form
 //   h = max(hdiag + s, e, f); t = h - beta; e' = max(e - alpha, t, 0);
 //   f' = max(f - alpha, t, 0); best = max(best, h)
 // Flooring E and F at 0 leaves H unchanged: H = max(0, ...) already, and by
 // induction the floored E is max(E, 0) because alpha >= 0.  Sharing
 // t = h - beta between E (next row) and F (next column) gives 7.5 VALU ops per
 // cell with a 3-input max, the running best taking one max3 per two cells.
+// The fp16 tier of the lane-per-subject kernel keeps its values in a frame
+// that moves by alpha per subject row and needs 6.5 (FrameStrip below).
 //
 // Two kernels:
 //  * inter_kernel: one lane per subject, two subjects per 32-bit lane in packed
@@ -39,12 +41,15 @@
 // magnitude, and floors at 0 hide them), so that cell's computed H is its true
 // value >= thr and the running best reaches thr.
 //   F16X2: fp16 holds every integer in [-2048, 2048]; thr = 1920 keeps
-//          thr - 1 + max(M) <= 2048 for |M| <= 127.  alpha and beta are
+//          thr - 1 + max(M) <= 2048 for |M| <= 127 (wave-per-pair kernel; the
+//          lane-per-subject row frame lowers it by 33 alpha).  alpha and beta are
 //          clamped to 2048: for lanes below thr a larger penalty gives the same
 //          (zero-floored) E and F.  Once flagged, values may round or reach
 //          +inf but never NaN (only finite constants are subtracted).
 //   I16X2: saturating int16; thr = 32767, the saturation ceiling.
 #include "sw_internal.h"
+
+#include <type_traits>
 
 namespace swmi {
 
@@ -242,6 +247,181 @@ struct Strip {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Row-frame form of the fp16 tier (lane-per-subject kernel).
+//
+// E loses alpha per subject row.  Storing every value of row r shifted by
+// c_r = r * alpha (r counted from the start of a period of kFrameRows rows)
+// cancels that decay: with H and F of row r at offset c_r, the E entering row
+// r at offset c_r, and H of row r-1 (the diagonal operand) at offset
+// c_r - alpha, made up for by a profile that holds s + alpha,
+//   h = max(hdiag + (s + alpha), e, f);   u = h + (alpha - beta);
+//   e' = max(e, u, c_r + alpha);          f' = max(f, u) - alpha
+// is Eq. 1 with e' at offset c_{r+1} = c_r + alpha and f' at offset c_r, and
+// one subtraction of a constant serves both gaps: 6.5 VALU ops per cell with
+// the running best instead of 7.5.  Only E is floored (at its offset of true
+// 0); F may go negative, which H never sees because E >= 0 (H = max(0, ...)
+// needs one floored operand).  Each period the carried H, E, floor and best
+// drop by kFrameRows * alpha; the running best is kept in the frame of the
+// current row (+alpha per row) and converted back at the end of a strip.
+//
+// Exactness: until the first cell whose true H reaches thr, every true value
+// lies in [-2048, thr + 126] and offsets add at most kFrameRows * alpha, so
+// thr = kThrF16 - (kFrameRows + 1) * alpha keeps all values exact integers in
+// fp16; that cell's offset H is exact and >= thr + c_r.  Rounding is monotone
+// and every offset applied is an exactly representable constant, so the
+// running best stays >= thr + its offset and the converted best >= thr: the
+// lane is flagged.  For alpha > kFrameFlagAlpha the ceiling is 0 and every
+// lane is flagged (values stay finite: offsets are at most 32 * 56).
+// ---------------------------------------------------------------------------
+struct FrameF16 {
+    h2 nalpha;    // -alpha
+    h2 palpha;    // +alpha
+    h2 nu;        // alpha - beta
+    h2 rebase;    // -kFrameRows * alpha
+    int bias;     // alpha, added to every profile score
+    __device__ FrameF16(int alpha, int beta) {
+        alpha = min(alpha, kFrameFlagAlpha);
+        beta = min(beta, 2048);
+        const _Float16 na = (_Float16)(float)(-alpha), pa = (_Float16)(float)alpha;
+        const _Float16 u = (_Float16)(float)(alpha - beta);
+        const _Float16 rb = (_Float16)(float)(-kFrameRows * alpha);
+        nalpha = h2{na, na};
+        palpha = h2{pa, pa};
+        nu = h2{u, u};
+        rebase = h2{rb, rb};
+        bias = alpha;
+    }
+};
+
+template <int T>
+struct FrameStrip {
+    typedef h2 V;
+    static __device__ __forceinline__ V max3(V a, V b, V c) {
+        return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
+    }
+
+    // One subject row across the strip (profile prefetch as in Strip::row).
+    // hb_prev = H(i-1, j0-1) at offset c_r - alpha, fin = F(i, j0) at offset
+    // c_r, fl = c_r + alpha; best at offset c_r.
+    static __device__ __forceinline__ void row(const FrameF16 &ops, V (&H)[T], V (&E)[T],
+                                               uint4 (&P)[T / 4], const uint4 *nxt,
+                                               uint32_t hb_prev, uint32_t fin, V fl, V &best,
+                                               uint32_t &hout, uint32_t &fout) {
+        V hdiag = as_v<V>(hb_prev);
+        V f = as_v<V>(fin);
+#pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) {
+            const uint32_t pv[4] = {P[j4].x, P[j4].y, P[j4].z, P[j4].w};
+            P[j4] = nxt[j4];
+#pragma unroll
+            for (int u = 0; u < 4; u += 2) {
+                const int j = j4 * 4 + u;
+                V h0, h1;
+                {
+                    const V hold = H[j];
+                    h0 = max3(hdiag + as_v<V>(pv[u]), E[j], f);
+                    const V t = h0 + ops.nu;
+                    E[j] = max3(E[j], t, fl);
+                    f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+                    H[j] = h0;
+                    hdiag = hold;
+                }
+                {
+                    const V hold = H[j + 1];
+                    h1 = max3(hdiag + as_v<V>(pv[u + 1]), E[j + 1], f);
+                    const V t = h1 + ops.nu;
+                    E[j + 1] = max3(E[j + 1], t, fl);
+                    f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+                    H[j + 1] = h1;
+                    hdiag = hold;
+                }
+                best = max3(best, h0, h1);
+            }
+        }
+        hout = as_u(H[T - 1]);
+        fout = as_u(f);
+#pragma unroll
+        for (int j = 0; j < T; ++j) asm volatile("" : "+v"(H[j]), "+v"(E[j]));
+        asm volatile("" : "+v"(best));
+    }
+
+    // All rows of one group against one strip; `best` is a true value on
+    // entry and exit.  Loads as in Strip::pass.
+    template <bool HAS_IN, bool HAS_OUT>
+    static __device__ __forceinline__ void pass(const FrameF16 &ops, V &best_io,
+                                                const uint16_t *codes, uint32_t *wsc, int nch,
+                                                const uint32_t *lds, int RS) {
+        constexpr int kPeriodChunks = kFrameRows / kChunk;
+        V H[T], E[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) { H[j] = ops.nalpha; E[j] = V{(_Float16)0.0f, (_Float16)0.0f}; }
+        V fl = ops.palpha;      // c_r + alpha
+        V z = ops.nalpha;       // true 0 at offset c_r - alpha: left edge of the first strip
+        V best = best_io;       // offset c_0 = 0
+        uint32_t hb_prev = as_u(ops.nalpha);
+        const int last = nch - 1;
+        uint2 cd = *(const uint2 *)codes;
+        uint2 cd_n = *(const uint2 *)(codes + (size_t)(last < 1 ? last : 1) * 256);
+        uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+        if (HAS_IN) {
+            b0 = ((const uint4 *)wsc)[0];
+            b1 = ((const uint4 *)wsc)[1];
+        }
+        uint4 P[T / 4];
+        {
+            const uint4 *src = (const uint4 *)(lds + (cd.x & 0xffffu) * RS);
+#pragma unroll
+            for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+        }
+        for (int c = 0; c < nch; ++c) {
+            if (c != 0 && c % kPeriodChunks == 0) {
+#pragma unroll
+                for (int j = 0; j < T; ++j) { H[j] += ops.rebase; E[j] += ops.rebase; }
+                fl += ops.rebase;
+                best += ops.rebase;
+                if (HAS_IN) hb_prev = as_u(as_v<V>(hb_prev) + ops.rebase);
+                else z += ops.rebase;
+            }
+            const int c1 = c + 1 < last ? c + 1 : last;
+            const int c2 = c + 2 < last ? c + 2 : last;
+            const uint2 cd_nn = *(const uint2 *)(codes + (size_t)c2 * 256);
+            uint4 b0n = make_uint4(0, 0, 0, 0), b1n = make_uint4(0, 0, 0, 0);
+            if (HAS_IN) {
+                b0n = ((const uint4 *)(wsc + (size_t)c1 * 512))[0];
+                b1n = ((const uint4 *)(wsc + (size_t)c1 * 512))[1];
+            }
+            const uint4 *nx[4] = {(const uint4 *)(lds + (cd.x >> 16) * RS),
+                                  (const uint4 *)(lds + (cd.y & 0xffffu) * RS),
+                                  (const uint4 *)(lds + (cd.y >> 16) * RS),
+                                  (const uint4 *)(lds + (cd_n.x & 0xffffu) * RS)};
+            const uint32_t hb_in[4] = {hb_prev, b0.x, b0.z, b1.x};
+            const uint32_t f_in[4] = {b0.y, b0.w, b1.y, b1.w};
+            uint32_t o[8];
+#pragma unroll
+            for (int x = 0; x < kChunk; ++x) {
+                row(ops, H, E, P, nx[x], HAS_IN ? hb_in[x] : as_u(z), HAS_IN ? f_in[x] : as_u(z),
+                    fl, best, o[2 * x], o[2 * x + 1]);
+                fl += ops.palpha;
+                best += ops.palpha;
+                if (!HAS_IN) z += ops.palpha;
+            }
+            hb_prev = b1.z;
+            if (HAS_OUT) {
+                uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
+                dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+                dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+            }
+            cd = cd_n;
+            cd_n = cd_nn;
+            b0 = b0n;
+            b1 = b1n;
+        }
+        // best is at offset c_last + alpha = fl - alpha
+        best_io = best - (fl + ops.nalpha);
+    }
+};
+
 // Occupancy the register budget is sized for (waves per SIMD).
 template <int T> struct InterOcc { static constexpr int value = T <= 16 ? 4 : (T <= 32 ? 2 : 1); };
 
@@ -269,7 +449,14 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
         const int it = s_item;
         if (it >= a.n_items) break;
         const int q = a.item_q[it];
-        const L ops(min(a.qs.gap[2 * q], kCap), min(a.qs.gap[2 * q + 1], kCap));
+        const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
+        typedef typename std::conditional<TIER == TIER_F16X2, FrameF16, L>::type Ops;
+        const Ops ops(min(alpha, kCap), min(beta, kCap));
+        int bias = 0, thr = a.thr;
+        if constexpr (TIER == TIER_F16X2) {
+            bias = ops.bias;
+            thr = frame_thr(a.thr, alpha);
+        }
         const int g = a.item_g[it] + w;
         const bool active = g < a.n_groups;
         const int rows = active ? a.grp_rows[g] : 0;
@@ -284,7 +471,7 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
             for (int e = threadIdx.x; e < R * (T / 2); e += W * 64) {
                 const int r = e / (T / 2), jj = e - r * (T / 2);
                 const int8_t *src = qp + (size_t)r * mp + k * T + 2 * jj;
-                stage[e] = (uint32_t)L::enc(src[0]) | ((uint32_t)L::enc(src[1]) << 16);
+                stage[e] = (uint32_t)L::enc(src[0] + bias) | ((uint32_t)L::enc(src[1] + bias) << 16);
             }
             __syncthreads();
             for (int e = threadIdx.x; e < RR * (T / 2); e += W * 64) {
@@ -300,7 +487,7 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
             if (!active) continue;
 
             const int nch = rows / kChunk;
-            typedef Strip<T, TIER> S;
+            typedef typename std::conditional<TIER == TIER_F16X2, FrameStrip<T>, Strip<T, TIER>>::type S;
             if (k == 0) {
                 if (nstrips == 1) S::template pass<false, false>(ops, best, codes, wsc, nch, lds, RS);
                 else S::template pass<false, true>(ops, best, codes, wsc, nch, lds, RS);
@@ -316,7 +503,7 @@ __global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(Inter
                 const int id = ids[half];
                 if (id < 0) continue;
                 bool flag;
-                const int v = L::value(best, half, a.thr, &flag);
+                const int v = L::value(best, half, thr, &flag);
                 a.scores[(size_t)q * a.n_seqs + id] = v;
                 if (flag) {
                     const int pos = atomicAdd(a.ovf_count, 1);

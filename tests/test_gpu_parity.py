@@ -103,6 +103,39 @@ def test_alphabets_and_penalties(swmi, orc, A, alpha, beta):
             db.close()
 
 
+@pytest.mark.parametrize("alpha", [28, 29, 56, 57, 300])
+def test_fp16_row_frame_alpha_range(swmi, orc, alpha):
+    """The fp16 lane-per-subject tier keeps values offset by up to 32 alpha, so
+    its ceiling is 1920 - 33 alpha and past alpha 56 every lane is flagged.
+    Forced onto that tier and on the planner's choice (int16 past alpha 28),
+    scores stay exact; subjects span many 32-row frame periods and include
+    copies of the query (scores far above every ceiling)."""
+    rng = np.random.Generator(np.random.PCG64(alpha))
+    A = 20
+    M = sd.blosum_style_matrix()
+    lens = rng.integers(1, 420, size=300)
+    seqs = [sd.random_residues(rng, int(L)) for L in lens]
+    q_long = sd.random_residues(rng, 300)
+    seqs[5] = q_long.copy()
+    seqs[77] = q_long[40:260].copy()
+    res, off = sd.pack_sequences(seqs)
+    for tier in (1, 0):
+        db = swmi.Database(res, off, A, long_threshold=-1)
+        try:
+            db.set_opts(tier=tier)
+            for q in [sd.random_residues(rng, 33), q_long]:
+                print(f"alpha={alpha} tier={tier} qlen={len(q)}", flush=True)
+                expect_equal(db.search(q, M, alpha, alpha + 10),
+                             orc.search(q, res, off, M, alpha, alpha + 10),
+                             f"alpha {alpha} tier {tier} qlen {len(q)}")
+                st = db.stats()
+                assert st["tier"] == (tier or (2 if alpha > 28 else 1))
+                if tier == 1 and alpha > 56:
+                    assert st["recomputed_pairs"] == 300
+        finally:
+            db.close()
+
+
 def test_asymmetric_matrix_orientation(swmi, orc):
     M = np.array([[0, 5], [-3, 0]], np.int8)
     res, off = sd.pack_sequences([np.array([1], np.uint8), np.array([0], np.uint8)])

@@ -10,9 +10,13 @@ and a lane whose exact score reaches the threshold is flagged (its computed
 best reaches the threshold too).  This model replays that arithmetic, cell
 order and all, in numpy float16 / int16, vectorised over many pairs of equal
 shape, and checks the claim against the oracle, including scores far beyond
-the fp16 and int16 ranges and penalties beyond the clamps.  It shares no code
-with the kernels or the oracle; it is a model of the design, written from the
-same recurrence (section II.A, Eq. 1).
+the fp16 and int16 ranges and penalties beyond the clamps.  The lane-per-
+subject fp16 tier uses a row-frame form of the same recurrence (values of
+subject row r offset by alpha * (r mod 32), so E needs no per-row decay); its
+model replays that arithmetic with strips, frame periods and padding, against
+the ceiling 1920 - 33 alpha, with a negative control at the unshifted ceiling.
+It shares no code with the kernels or the oracle; it is a model of the design,
+written from the same recurrence (section II.A, Eq. 1).
 """
 import numpy as np
 import pytest
@@ -76,8 +80,95 @@ def model_i16(Q, S, M, alpha, beta):
     return best
 
 
+def frame_ceiling(thr, alpha, rows=32):
+    """Ceiling of the row-frame fp16 tier for a query with gap extension alpha."""
+    if alpha > 56:
+        return 0
+    return min(thr, 1920 - (rows + 1) * alpha)
+
+
+def model_f16_frame(Q, S, M, alpha, beta, T=8, rows=32, chunk=4):
+    """Row-frame fp16 arithmetic of the lane-per-subject kernel, replayed in
+    numpy float16: the query in strips of T columns (boundary H and F of every
+    row handed to the next strip), subjects padded with zero-score rows to a
+    multiple of `chunk` plus one extra chunk, the query with zero-score columns
+    to a multiple of T, profile scores biased by +alpha, values of subject row
+    r offset by alpha * (r mod rows), and the carried state lowered by
+    rows * alpha at the start of every period.  Returns the converted best."""
+    B, m = Q.shape
+    n = S.shape[1]
+    f16 = np.float16
+    a = min(alpha, 56)
+    b = min(beta, 2048)
+    nalpha, palpha, nu, rb = f16(-a), f16(a), f16(a - b), f16(-rows * a)
+    A = M.shape[0]
+    Mx = np.zeros((A + 1, A + 1), np.int64)          # code A pads, scoring 0
+    Mx[:A, :A] = M
+    n_pad = ((n + chunk - 1) // chunk) * chunk + chunk
+    m_pad = ((m + T - 1) // T) * T
+    Qp = np.full((B, m_pad), A, np.int64)
+    Qp[:, :m] = Q
+    Sp = np.full((B, n_pad), A, np.int64)
+    Sp[:, :n] = S
+    prof = [(Mx[Qp, Sp[:, r:r + 1]] + a).astype(f16) for r in range(n_pad)]   # (B, m_pad) per row
+    best_true = np.zeros(B, f16)
+    hb_out = f_out = None
+    with np.errstate(over="ignore", invalid="ignore"):
+        for k in range(m_pad // T):
+            has_in = k > 0
+            H = np.full((T, B), nalpha, f16)
+            E = np.zeros((T, B), f16)
+            fl = np.full(B, palpha, f16)
+            z = np.full(B, nalpha, f16)
+            best = best_true.copy()
+            hb_prev = np.full(B, nalpha, f16)
+            new_hb, new_f = [], []
+            for r in range(n_pad):
+                if r and r % rows == 0:
+                    H = (H + rb).astype(f16)
+                    E = (E + rb).astype(f16)
+                    fl = (fl + rb).astype(f16)
+                    best = (best + rb).astype(f16)
+                    if has_in:
+                        hb_prev = (hb_prev + rb).astype(f16)
+                    else:
+                        z = (z + rb).astype(f16)
+                if has_in:
+                    hdiag = hb_prev if r % chunk == 0 else hb_out[r - 1]
+                    f = f_out[r]
+                else:
+                    hdiag, f = z, z
+                for jj in range(T):
+                    j = k * T + jj
+                    hold = H[jj].copy()
+                    h = np.maximum(np.maximum((hdiag + prof[r][:, j]).astype(f16), E[jj]), f)
+                    t = (h + nu).astype(f16)
+                    E[jj] = np.maximum(np.maximum(E[jj], t), fl)
+                    f = (np.maximum(f, t) + nalpha).astype(f16)
+                    H[jj] = h
+                    hdiag = hold
+                    best = np.maximum(best, h)
+                new_hb.append(H[T - 1].copy())
+                new_f.append(f.copy())
+                fl = (fl + palpha).astype(f16)
+                best = (best + palpha).astype(f16)
+                if not has_in:
+                    z = (z + palpha).astype(f16)
+                if has_in and r % chunk == chunk - 1:
+                    hb_prev = hb_out[r]
+            best_true = (best - (fl + nalpha).astype(f16)).astype(f16)
+            hb_out, f_out = new_hb, new_f
+    assert not np.isnan(best_true).any()
+    return best_true
+
+
 def check_claim(orc, Q, S, M, alpha, beta, thr, tier):
-    best = model_f16(Q, S, M, alpha, beta) if tier == "f16" else model_i16(Q, S, M, alpha, beta)
+    if tier == "f16":
+        best = model_f16(Q, S, M, alpha, beta)
+    elif tier == "frame":
+        best = model_f16_frame(Q, S, M, alpha, beta)
+    else:
+        best = model_i16(Q, S, M, alpha, beta)
     for x in range(Q.shape[0]):
         exact = orc.sw_score(Q[x], S[x], M, alpha, beta)
         flagged = not (float(best[x]) < thr)
@@ -153,3 +244,57 @@ def test_model_rejects_an_invalid_fp16_threshold(orc):
     Q[1::4, :25] = rng.integers(0, A, size=(12, 25))   # scores between 2048 and 4000 round in fp16
     with pytest.raises(AssertionError):
         check_claim(orc, Q, S, M, 2, 12, 4000, "f16")
+
+
+@pytest.mark.parametrize("thr", [1920, 700, 150])
+def test_f16_row_frame_random(orc, thr):
+    """Row-frame fp16 tier: subjects span several 32-row periods, the query
+    several strips; penalties across the ceiling's range (alpha 0..200)."""
+    rng = np.random.Generator(np.random.PCG64(thr + 11))
+    for A, lo, hi in [(20, -4, 11), (4, -127, 127)]:
+        M = rng.integers(lo, hi + 1, size=(A, A)).astype(np.int8)
+        Q = rng.integers(0, A, size=(48, 21)).astype(np.uint8)
+        S = rng.integers(0, A, size=(48, 75)).astype(np.uint8)
+        for alpha, beta in [(0, 0), (2, 12), (5, 5), (28, 40), (29, 3000), (56, 60), (57, 57), (200, 9000)]:
+            check_claim(orc, Q, S, M, alpha, beta, frame_ceiling(thr, alpha), "frame")
+
+
+def test_f16_row_frame_scores_beyond_range(orc):
+    """Copies and near-copies under a high diagonal: true scores from a few
+    hundred to far past 2048 (and past the fp16 maximum); every lane at or
+    above the ceiling must be flagged, every other exact."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    A = 5
+    M = np.full((A, A), -3, np.int8)
+    np.fill_diagonal(M, 100)
+    base = rng.integers(0, A, size=(40, 70)).astype(np.uint8)
+    Q = base[:, :24].copy()
+    S = base.copy()
+    S[:, 30:54] = Q                     # the query planted mid-subject
+    S[::3, 33::5] = (S[::3, 33::5] + 1) % A
+    Q[1::4, :12] = rng.integers(0, A, size=(10, 12))
+    for alpha in (1, 2, 20):
+        check_claim(orc, Q, S, M, alpha, alpha + 10, frame_ceiling(1920, alpha), "frame")
+    Qb = np.tile(np.arange(A, dtype=np.uint8), (3, 140))[:, :700]
+    check_claim(orc, Qb[:, :40], Qb, M, 2, 12, frame_ceiling(1920, 2), "frame")
+
+
+def test_frame_model_rejects_the_unshifted_ceiling(orc):
+    """Negative control: with the ceiling of the unshifted form (1920) and
+    alpha 20, an odd score of 1797 reached late in a 32-row period sits at an
+    offset of up to 620, past 2048 where fp16 keeps only even integers, so
+    unflagged lanes come out wrong; the frame ceiling (1260) flags them all."""
+    rng = np.random.Generator(np.random.PCG64(9))
+    A = 5
+    M = np.full((A, A), -3, np.int8)
+    np.fill_diagonal(M, 100)
+    B = 64
+    Q = rng.integers(0, A, size=(B, 19)).astype(np.uint8)
+    S = rng.integers(0, A, size=(B, 70)).astype(np.uint8)
+    for x in range(B):
+        p = 20 + (x % 30)                   # the alignment ends at row p + 18
+        S[x, p:p + 19] = Q[x]
+        S[x, p + 3 + (x % 13)] = (S[x, p + 3 + (x % 13)] + 1) % A   # one mismatch: 1797
+    check_claim(orc, Q, S, M, 20, 30, frame_ceiling(1920, 20), "frame")
+    with pytest.raises(AssertionError):
+        check_claim(orc, Q, S, M, 20, 30, 1920, "frame")
