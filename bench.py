@@ -38,7 +38,10 @@ sys.path.insert(0, ROOT)
 CUS, CLOCK_GHZ = 256, 2.4
 PEAK_LANE_OPS = CUS * 64 * CLOCK_GHZ * 1e9          # 32-bit VALU lane-ops/s (39.3 T)
 PEAK_HALF_OPS = 2 * PEAK_LANE_OPS                    # packed 16-bit lane-ops/s (78.6 T)
-OPS_PER_CELL = 7.5                                   # add, max3, sub, 2x(sub+max3), max3/2
+# VALU ops per cell of the fp16 row-frame form that the lane-per-subject
+# kernel evaluates: hdiag+s, max3 (H), h+(alpha-beta), max3 (E), max3+add (F),
+# and one max3 per two cells for the running best.
+OPS_PER_CELL = 6.5
 PEAK_GCUPS_F16X2 = PEAK_HALF_OPS / OPS_PER_CELL / 1e9
 
 

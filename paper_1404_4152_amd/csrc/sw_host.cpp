@@ -372,7 +372,7 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
     Launch L;
     L.plan = plan;
     L.Ti = intra_T_for(max_qlen);
-    L.grid_inter = (int)std::min<int64_t>(n_inter, inter_max_grid(db->R, plan.strip, plan.waves));
+    L.grid_inter = (int)std::min<int64_t>(n_inter, inter_max_grid(db->R, plan.tier, plan.strip, plan.waves));
     const int per_cu = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, L.Ti) + 64), 8));
     L.grid_long = (int)std::min<int64_t>(n_intra, (int64_t)per_cu * db->cus);
     const int per_cu16 = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, 16) + 64), 8));
@@ -542,7 +542,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     std::vector<int32_t> slots(nq);
     std::iota(slots.begin(), slots.end(), 0);
     std::vector<int32_t> long_ids;
-    const int resident = inter_max_grid(db->R, plan.strip, plan.waves) * plan.waves;
+    const int resident = inter_max_grid(db->R, plan.tier, plan.strip, plan.waves) * plan.waves;
     const int64_t g_cut = route_cut(db, plan, mpad, resident, long_ids);
     Items it;
     const int64_t nblk = (g_cut + plan.waves - 1) / plan.waves;
@@ -775,7 +775,7 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
     std::map<int, double> best_gcups;
     // Time every stride-th block only, but keep at least 16 items per resident
     // workgroup: with fewer, the tail of the work queue, not the plan, decides.
-    const int64_t resident = inter_max_grid(db->R, 32, 4);
+    const int64_t resident = inter_max_grid(db->R, TIER_F16X2, 32, 4);
     const int64_t stride =
         std::max<int64_t>(1, std::min<int64_t>(8, (db->n_groups / 4) / (16 * resident)));
     uint32_t lcg = 12345u;
@@ -898,7 +898,7 @@ int server_setup(sw_server *s) {
         // route as if half the slots held 400-residue queries
         const int slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
         std::vector<int32_t> mp(std::max(1, slots / 2), 448);
-        const int resident = inter_max_grid(db->R, s->plan.strip, W) * W;
+        const int resident = inter_max_grid(db->R, s->plan.tier, s->plan.strip, W) * W;
         s->g_cut = route_cut(db, s->plan, mp, resident, s->long_ids);
     }
     s->blocks = (s->g_cut + W - 1) / W;

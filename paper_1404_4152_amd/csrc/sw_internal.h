@@ -97,7 +97,7 @@ hipError_t prepare_kernels();
 hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
                         hipStream_t st);
 int inter_lds_bytes(int R, int strip);
-int inter_max_grid(int R, int strip, int waves);      // resident workgroups that fit
+int inter_max_grid(int R, int tier, int strip, int waves);   // resident workgroups that fit
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);

@@ -423,10 +423,13 @@ struct FrameStrip {
 };
 
 // Occupancy the register budget is sized for (waves per SIMD).
-template <int T> struct InterOcc { static constexpr int value = T <= 16 ? 4 : (T <= 32 ? 2 : 1); };
+// The fp16 row frame needs a few more registers than 128 at strip 16.
+template <int T, int TIER> struct InterOcc {
+    static constexpr int value = T <= 16 ? (TIER == TIER_F16X2 ? 3 : 4) : (T <= 32 ? 2 : 1);
+};
 
 template <int T, int W, int TIER>
-__global__ void __launch_bounds__(W * 64, InterOcc<T>::value) inter_kernel(InterArgs a, int magic) {
+__global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kernel(InterArgs a, int magic) {
     typedef Lane<TIER> L;
     typedef typename L::V V;
     constexpr int RS = T + 4;                 // dwords per pair-profile row (padded)
@@ -523,16 +526,38 @@ int inter_lds_bytes(int R, int strip) {
 
 static int lds_per_cu() { return 160 * 1024; }
 
-int inter_max_grid(int R, int strip, int waves) {
+template <int T, int W, int TIER>
+static int inter_resident_t(int R) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inter_kernel<T, W, TIER>, W * 64,
+                                                     inter_lds_bytes(R, T)) != hipSuccess)
+        per_cu = 0;
+    return per_cu;
+}
+
+int inter_max_grid(int R, int tier, int strip, int waves) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t p;
         if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
     }
-    const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip) + 64);
-    const int by_waves = 32 / waves;   // conservative: 8 waves per SIMD at most
-    int per_cu = by_lds < by_waves ? by_lds : by_waves;
-    if (per_cu < 1) per_cu = 1;
+    // workgroups of this variant that fit on one CU (registers, LDS, waves)
+    int per_cu = 0;
+#define SWMI_RES_CASE(T_, W_)                                                              \
+    if (strip == T_ && waves == W_)                                                        \
+        per_cu = tier == TIER_I16X2 ? inter_resident_t<T_, W_, TIER_I16X2>(R)             \
+                                    : inter_resident_t<T_, W_, TIER_F16X2>(R);
+    SWMI_RES_CASE(16, 4) SWMI_RES_CASE(16, 8)
+    SWMI_RES_CASE(32, 4) SWMI_RES_CASE(32, 6) SWMI_RES_CASE(32, 8)
+    SWMI_RES_CASE(64, 4)
+#undef SWMI_RES_CASE
+    if (per_cu < 1) {
+        // runtime query unavailable: bound by LDS and 8 waves per SIMD
+        const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip) + 64);
+        const int by_waves = 32 / waves;
+        per_cu = by_lds < by_waves ? by_lds : by_waves;
+        if (per_cu < 1) per_cu = 1;
+    }
     return per_cu * cus;
 }
 
