@@ -136,21 +136,22 @@ struct Strip {
     typedef Lane<TIER> L;
     typedef typename L::V V;
 
-    // One subject row across the strip.  P holds this row's pair-profile
-    // values; each 4-column slot is refilled with the next row's values
-    // (`nxt`) as soon as it has been consumed, so the LDS latency hides behind
-    // a full row of arithmetic with only T/4 uint4 registers.
+    // One subject row across the strip.  Pc holds this row's pair-profile
+    // values; the next row's (`nxt`) are loaded into Pn at the start, so the
+    // LDS latency hides behind a full row of arithmetic.  The two buffers
+    // alternate row by row and stay in fixed registers.
     // hb_prev = H(i-1, j0-1), fin = F(i, j0).  Returns H(i, j0+T-1), F(i, j0+T).
     static __device__ __forceinline__ void row(const L &ops, V (&H)[T], V (&E)[T],
-                                               uint4 (&P)[T / 4], const uint4 *nxt,
-                                               uint32_t hb_prev, uint32_t fin, V &best,
-                                               uint32_t &hout, uint32_t &fout) {
+                                               const uint4 (&Pc)[T / 4], uint4 (&Pn)[T / 4],
+                                               const uint4 *nxt, uint32_t hb_prev, uint32_t fin,
+                                               V &best, uint32_t &hout, uint32_t &fout) {
         V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) Pn[j4] = nxt[j4];
+#pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) {
-            const uint32_t pv[4] = {P[j4].x, P[j4].y, P[j4].z, P[j4].w};
-            P[j4] = nxt[j4];
+            const uint32_t pv[4] = {Pc[j4].x, Pc[j4].y, Pc[j4].z, Pc[j4].w};
 #pragma unroll
             for (int u = 0; u < 4; u += 2) {
                 const int j = j4 * 4 + u;
@@ -206,11 +207,11 @@ struct Strip {
             b0 = ((const uint4 *)wsc)[0];
             b1 = ((const uint4 *)wsc)[1];
         }
-        uint4 P[T / 4];
+        uint4 P0[T / 4], P1[T / 4];
         {
             const uint4 *src = (const uint4 *)(lds + (cd.x & 0xffffu) * RS);
 #pragma unroll
-            for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+            for (int j4 = 0; j4 < T / 4; ++j4) P0[j4] = src[j4];
         }
         for (int c = 0; c < nch; ++c) {
             const int c1 = c + 1 < last ? c + 1 : last;
@@ -226,13 +227,13 @@ struct Strip {
             const uint4 *n3 = (const uint4 *)(lds + (cd.y >> 16) * RS);
             const uint4 *n4 = (const uint4 *)(lds + (cd_n.x & 0xffffu) * RS);
             uint32_t o[8];
-            row(ops, H, E, P, n1, hb_prev, b0.y, best, o[0], o[1]);
+            row(ops, H, E, P0, P1, n1, hb_prev, b0.y, best, o[0], o[1]);
             hb_prev = b0.x;
-            row(ops, H, E, P, n2, hb_prev, b0.w, best, o[2], o[3]);
+            row(ops, H, E, P1, P0, n2, hb_prev, b0.w, best, o[2], o[3]);
             hb_prev = b0.z;
-            row(ops, H, E, P, n3, hb_prev, b1.y, best, o[4], o[5]);
+            row(ops, H, E, P0, P1, n3, hb_prev, b1.y, best, o[4], o[5]);
             hb_prev = b1.x;
-            row(ops, H, E, P, n4, hb_prev, b1.w, best, o[6], o[7]);
+            row(ops, H, E, P1, P0, n4, hb_prev, b1.w, best, o[6], o[7]);
             hb_prev = b1.z;
             if (HAS_OUT) {
                 uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
@@ -301,41 +302,42 @@ struct FrameStrip {
         return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
     }
 
-    // One subject row across the strip (profile prefetch as in Strip::row).
+    // One cell in the row frame; hdiag and f carry along the row.
+    static __device__ __forceinline__ V cell(const FrameF16 &ops, V &H, V &E, uint32_t s, V &hdiag,
+                                             V &f, V fl) {
+        const V hold = H;
+        const V h = max3(hdiag + as_v<V>(s), E, f);
+        const V t = h + ops.nu;
+        E = max3(E, t, fl);
+        f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+        H = h;
+        hdiag = hold;
+        return h;
+    }
+
+    // One subject row across the strip: Pc holds this row's pair-profile
+    // values, and the next row's are loaded into Pn at the start so the LDS
+    // latency hides behind the row.  Alternating the two buffers row by row
+    // keeps every value in fixed registers (a single buffer refilled in place
+    // makes the compiler copy it back at every loop edge).
     // hb_prev = H(i-1, j0-1) at offset c_r - alpha, fin = F(i, j0) at offset
     // c_r, fl = c_r + alpha; best at offset c_r.
     static __device__ __forceinline__ void row(const FrameF16 &ops, V (&H)[T], V (&E)[T],
-                                               uint4 (&P)[T / 4], const uint4 *nxt,
-                                               uint32_t hb_prev, uint32_t fin, V fl, V &best,
-                                               uint32_t &hout, uint32_t &fout) {
+                                               const uint4 (&Pc)[T / 4], uint4 (&Pn)[T / 4],
+                                               const uint4 *nxt, uint32_t hb_prev, uint32_t fin,
+                                               V fl, V &best, uint32_t &hout, uint32_t &fout) {
         V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) Pn[j4] = nxt[j4];
+#pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) {
-            const uint32_t pv[4] = {P[j4].x, P[j4].y, P[j4].z, P[j4].w};
-            P[j4] = nxt[j4];
+            const uint32_t pv[4] = {Pc[j4].x, Pc[j4].y, Pc[j4].z, Pc[j4].w};
 #pragma unroll
             for (int u = 0; u < 4; u += 2) {
                 const int j = j4 * 4 + u;
-                V h0, h1;
-                {
-                    const V hold = H[j];
-                    h0 = max3(hdiag + as_v<V>(pv[u]), E[j], f);
-                    const V t = h0 + ops.nu;
-                    E[j] = max3(E[j], t, fl);
-                    f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
-                    H[j] = h0;
-                    hdiag = hold;
-                }
-                {
-                    const V hold = H[j + 1];
-                    h1 = max3(hdiag + as_v<V>(pv[u + 1]), E[j + 1], f);
-                    const V t = h1 + ops.nu;
-                    E[j + 1] = max3(E[j + 1], t, fl);
-                    f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
-                    H[j + 1] = h1;
-                    hdiag = hold;
-                }
+                const V h0 = cell(ops, H[j], E[j], pv[u], hdiag, f, fl);
+                const V h1 = cell(ops, H[j + 1], E[j + 1], pv[u + 1], hdiag, f, fl);
                 best = max3(best, h0, h1);
             }
         }
@@ -368,11 +370,11 @@ struct FrameStrip {
             b0 = ((const uint4 *)wsc)[0];
             b1 = ((const uint4 *)wsc)[1];
         }
-        uint4 P[T / 4];
+        uint4 P0[T / 4], P1[T / 4];
         {
             const uint4 *src = (const uint4 *)(lds + (cd.x & 0xffffu) * RS);
 #pragma unroll
-            for (int j4 = 0; j4 < T / 4; ++j4) P[j4] = src[j4];
+            for (int j4 = 0; j4 < T / 4; ++j4) P0[j4] = src[j4];
         }
         for (int c = 0; c < nch; ++c) {
             if (c != 0 && c % kPeriodChunks == 0) {
@@ -400,8 +402,9 @@ struct FrameStrip {
             uint32_t o[8];
 #pragma unroll
             for (int x = 0; x < kChunk; ++x) {
-                row(ops, H, E, P, nx[x], HAS_IN ? hb_in[x] : as_u(z), HAS_IN ? f_in[x] : as_u(z),
-                    fl, best, o[2 * x], o[2 * x + 1]);
+                const uint32_t hb = HAS_IN ? hb_in[x] : as_u(z), fi = HAS_IN ? f_in[x] : as_u(z);
+                if (x & 1) row(ops, H, E, P1, P0, nx[x], hb, fi, fl, best, o[2 * x], o[2 * x + 1]);
+                else row(ops, H, E, P0, P1, nx[x], hb, fi, fl, best, o[2 * x], o[2 * x + 1]);
                 fl += ops.palpha;
                 best += ops.palpha;
                 if (!HAS_IN) z += ops.palpha;
@@ -743,52 +746,144 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 // Packed-fp16 wave-per-pair kernel: the systolic schedule above with one
 // subject in each 16-bit half of every lane (same query), so one instruction
 // advances two alignments.  The two halves read their substitution scores from
-// two profile rows; one v_perm per column pair packs them.  Exactness as in the
-// lane-per-subject f16x2 tier: a half whose best reaches thr is flagged and
-// recomputed in int32.
+// two profile rows; one v_perm per column pair packs them.
+//
+// It evaluates the row-frame form of the lane-per-subject fp16 tier.  Lane l
+// works on subject row t - l at step t, so the offset of that row is taken as
+// alpha * ((t mod kFrameRows) - l): it grows by alpha per step, so E needs no
+// decay, it is the same for every lane that handles the row (H and F cross to
+// lane l+1 one step later), and it drops by kFrameRows * alpha for every lane
+// at once at the end of each block of kFrameRows steps, outputs included.
+// Offsets span [-63 alpha, 32 alpha]; for alpha <= kFrameMaxAlpha every value
+// that can matter stays an exact fp16 integer with thr = 1920 - 33 alpha, and
+// a value below -2048 rounds to one that is still below the frame's zero.
+// Larger alpha flags every half for the exact recompute.  Pass boundaries are
+// stored as true values and converted on the way in and out.
 // ---------------------------------------------------------------------------
 template <int T>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
-                                           const uint2 *pb, const Lane<TIER_F16X2> &ops,
-                                           uint32_t hb_prev, uint32_t fin, h2 &best,
-                                           uint32_t &hout, uint32_t &fout) {
-    h2 hdiag = as_v<h2>(hb_prev);
-    h2 f = as_v<h2>(fin);
+                                           const uint2 *pb, const FrameF16 &ops, h2 hdiag, h2 f,
+                                           h2 fl, h2 &best, h2 &hout, h2 &fout) {
+    // (low half from subject a's row, high half from subject b's row)
+    uint32_t sv[T];
 #pragma unroll
     for (int j4 = 0; j4 < T / 4; ++j4) {
         const uint2 A = pa[j4], B = pb[j4];
-        // (low half from subject a's row, high half from subject b's row)
-        const uint32_t sv[4] = {__builtin_amdgcn_perm(B.x, A.x, 0x05040100u),
-                                __builtin_amdgcn_perm(B.x, A.x, 0x07060302u),
-                                __builtin_amdgcn_perm(B.y, A.y, 0x05040100u),
-                                __builtin_amdgcn_perm(B.y, A.y, 0x07060302u)};
+        sv[4 * j4 + 0] = __builtin_amdgcn_perm(B.x, A.x, 0x05040100u);
+        sv[4 * j4 + 1] = __builtin_amdgcn_perm(B.x, A.x, 0x07060302u);
+        sv[4 * j4 + 2] = __builtin_amdgcn_perm(B.y, A.y, 0x05040100u);
+        sv[4 * j4 + 3] = __builtin_amdgcn_perm(B.y, A.y, 0x07060302u);
+    }
+    // The diagonal operand of column j+1 is taken from H[j] before H[j] is
+    // overwritten, so each new H goes into the register of the old one.
+    h2 d = hdiag + as_v<h2>(sv[0]);
+    h2 hp = d;
 #pragma unroll
-        for (int u = 0; u < 4; u += 2) {
-            const int j = j4 * 4 + u;
-            h2 h0, h1;
-            {
-                const h2 hold = H[j];
-                h0 = ops.hmax(ops.diag(hdiag, as_v<h2>(sv[u])), E[j], f);
-                const h2 t = ops.open(h0);
-                E[j] = ops.gap(E[j], t);
-                f = ops.gap(f, t);
-                H[j] = h0;
-                hdiag = hold;
+    for (int j = 0; j < T; ++j) {
+        const h2 dn = j + 1 < T ? H[j] + as_v<h2>(sv[j + 1]) : d;
+        const h2 h = FrameStrip<4>::max3(d, E[j], f);
+        const h2 t = h + ops.nu;
+        E[j] = FrameStrip<4>::max3(E[j], t, fl);
+        f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+        H[j] = h;
+        if (j & 1) best = FrameStrip<4>::max3(best, hp, h);
+        hp = h;
+        d = dn;
+    }
+    hout = H[T - 1];
+    fout = f;
+}
+
+template <int T, bool HAS_IN, bool HAS_OUT>
+__device__ __forceinline__ void intra2_pass(const IntraArgs &a, const FrameF16 &ops,
+                                            const uint16_t *prof, int RS, int32_t *wsc,
+                                            const uint8_t *sa, const uint8_t *sb, int na, int nb,
+                                            int pad, h2 &best_io) {
+    const int lane = threadIdx.x & 63;
+    const int n = na > nb ? na : nb;
+    const int nblk = (n + 63) / 64;
+    const int steps = HAS_OUT ? nblk * 64 + 63 : n + 63;
+    const h2 pa2 = ops.palpha;
+    const float alpha = (float)ops.bias;
+    // Offset of this lane at step 0, and the per-lane conversions of the
+    // lane-0 feeders (row consumed at step row: alpha * (row mod 32)) and of
+    // the collected last-lane outputs (row produced by lane 63 at step row+63).
+    const _Float16 o0 = (_Float16)(-alpha * lane);
+    const _Float16 fc = (_Float16)(alpha * (lane & (kFrameRows - 1)));
+    const _Float16 wc = (_Float16)(alpha * (((lane - 1) & (kFrameRows - 1)) - 63));
+    const h2 off0 = h2{o0, o0}, fconv = h2{fc, fc}, wconv = h2{wc, wc};
+    h2 H[T], E[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) { H[j] = off0 + ops.nalpha; E[j] = off0; }
+    h2 fl = off0 + pa2;
+    h2 best = best_io + off0;
+    h2 hb_prev = off0 + ops.nalpha;
+    // outputs handed to lane l+1 before step 0 stand for step -1 of lane l:
+    // true 0 at offset -alpha * (l + 1)
+    h2 hout = off0 + ops.nalpha, fout = off0 + ops.nalpha;
+    int r = pad | (pad << 8);   // residue codes of both subjects, a in the low byte
+    int cH = 0, cF = 0;
+    auto feed = [&](int row, int &fr, int &fh, int &ff) {
+        const int ra = row < na ? sa[row] : pad;
+        const int rb = row < nb ? sb[row] : pad;
+        fr = ra | (rb << 8);
+        h2 vh = fconv, vf = fconv;
+        if (HAS_IN && row < n) {
+            vh += as_v<h2>((uint32_t)wsc[2 * row]);
+            vf += as_v<h2>((uint32_t)wsc[2 * row + 1]);
+        }
+        fh = (int)as_u(vh);
+        ff = (int)as_u(vf);
+    };
+    int fR, fH, fF, nR, nH, nF;
+    feed(lane, fR, fH, fF);
+    feed(64 + lane, nR, nH, nF);
+    for (int tb = 0; tb < steps; tb += kFrameRows) {
+        if (tb > 0 && (tb & 63) == 0) {
+            fR = nR; fH = nH; fF = nF;
+            feed(tb + 64 + lane, nR, nH, nF);
+        }
+        const int ue = steps - tb < kFrameRows ? steps - tb : kFrameRows;
+        for (int u = 0; u < ue; ++u) {
+            r = shr1(fR, r);
+            const h2 hin = as_v<h2>((uint32_t)shr1(fH, (int)as_u(hout)));
+            const h2 fin = as_v<h2>((uint32_t)shr1(fF, (int)as_u(fout)));
+            fR = shl1(fR, fR);
+            fH = shl1(fH, fH);
+            fF = shl1(fF, fF);
+            const uint2 *pa = (const uint2 *)(prof + (r & 0xff) * RS + lane * T);
+            const uint2 *pb = (const uint2 *)(prof + (r >> 8) * RS + lane * T);
+            intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, fl, best, hout, fout);
+            hb_prev = hin;
+            fl += pa2;
+            best += pa2;
+            if (HAS_OUT) {
+                cH = shl1((int)as_u(hout), cH);
+                cF = shl1((int)as_u(fout), cF);
+                const int t = tb + u;
+                if ((t & 63) == 62 && t >= 126) {
+                    const int row = t - 126 + lane;
+                    wsc[2 * row] = (int)as_u(as_v<h2>((uint32_t)cH) - wconv);
+                    wsc[2 * row + 1] = (int)as_u(as_v<h2>((uint32_t)cF) - wconv);
+                }
             }
-            {
-                const h2 hold = H[j + 1];
-                h1 = ops.hmax(ops.diag(hdiag, as_v<h2>(sv[u + 1])), E[j + 1], f);
-                const h2 t = ops.open(h1);
-                E[j + 1] = ops.gap(E[j + 1], t);
-                f = ops.gap(f, t);
-                H[j + 1] = h1;
-                hdiag = hold;
+        }
+        if (ue == kFrameRows) {
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                H[j] += ops.rebase;
+                E[j] += ops.rebase;
             }
-            best = ops.best2(best, h0, h1);
+            fl += ops.rebase;
+            best += ops.rebase;
+            hb_prev += ops.rebase;
+            hout += ops.rebase;
+            fout += ops.rebase;
         }
     }
-    hout = as_u(H[T - 1]);
-    fout = as_u(f);
+    // best is at the offset of step `steps`
+    const _Float16 oe = (_Float16)(alpha * ((steps & (kFrameRows - 1)) - lane));
+    best_io = best - h2{oe, oe};
 }
 
 template <int T, int W>
@@ -822,8 +917,9 @@ __global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
         const int mp = a.qs.mpad[q];
         const int npass = (a.qs.qlen[q] + PW - 1) / PW;
         const int8_t *qp = a.qs.qp[q];
-        constexpr int kCap = 2048;
-        const L ops(min(a.qs.gap[2 * q], kCap), min(a.qs.gap[2 * q + 1], kCap));
+        const int alpha = a.qs.gap[2 * q];
+        const FrameF16 ops(min(alpha, kFrameMaxAlpha), min(a.qs.gap[2 * q + 1], 2048));
+        const int thr = alpha > kFrameMaxAlpha ? 0 : frame_thr(a.thr, alpha);
         h2 best = L::zero();
 
         for (int p = 0; p < npass; ++p) {
@@ -831,54 +927,17 @@ __global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
             for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
                 const int r = e / PW, c = e - r * PW;
                 const int col = p * PW + c;
-                prof[r * RS + c] = L::enc(col < mp ? (int)qp[(size_t)r * mp + col] : 0);
+                prof[r * RS + c] = L::enc((col < mp ? (int)qp[(size_t)r * mp + col] : 0) + ops.bias);
             }
             __syncthreads();
             if (n <= 0) continue;
-
             const bool has_in = p > 0, has_out = p + 1 < npass;
-            const int nblk = (n + 63) / 64;
-            const int steps = has_out ? nblk * 64 + 63 : n + 63;
-            h2 H[T], E[T];
-#pragma unroll
-            for (int j = 0; j < T; ++j) { H[j] = L::zero(); E[j] = L::zero(); }
-            uint32_t hb_prev = 0, hout = 0, fout = 0;
-            int r = pad | (pad << 8);   // residue codes of both subjects, a in the low byte
-            int cH = 0, cF = 0;
-            auto feed = [&](int row, int &fr, int &fh, int &ff) {
-                const int ra = row < na ? sa[row] : pad;
-                const int rb = row < nb ? sb[row] : pad;
-                fr = ra | (rb << 8);
-                fh = (has_in && row < n) ? wsc[2 * row] : 0;
-                ff = (has_in && row < n) ? wsc[2 * row + 1] : 0;
-            };
-            int fR, fH, fF, nR, nH, nF;
-            feed(lane, fR, fH, fF);
-            feed(64 + lane, nR, nH, nF);
-            for (int t = 0; t < steps; ++t) {
-                if (t > 0 && (t & 63) == 0) {
-                    fR = nR; fH = nH; fF = nF;
-                    feed(t + 64 + lane, nR, nH, nF);
-                }
-                r = shr1(fR, r);
-                const int hin = shr1(fH, (int)hout);
-                const int fin = shr1(fF, (int)fout);
-                fR = shl1(fR, fR);
-                fH = shl1(fH, fH);
-                fF = shl1(fF, fF);
-                const uint2 *pa = (const uint2 *)(prof + (r & 0xff) * RS + lane * T);
-                const uint2 *pb = (const uint2 *)(prof + (r >> 8) * RS + lane * T);
-                intra2_row<T>(H, E, pa, pb, ops, hb_prev, (uint32_t)fin, best, hout, fout);
-                hb_prev = (uint32_t)hin;
-                if (has_out) {
-                    cH = shl1((int)hout, cH);
-                    cF = shl1((int)fout, cF);
-                    if ((t & 63) == 62 && t >= 126) {
-                        const int row = t - 126 + lane;
-                        wsc[2 * row] = cH;
-                        wsc[2 * row + 1] = cF;
-                    }
-                }
+            if (has_in) {
+                if (has_out) intra2_pass<T, true, true>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, true, false>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
+            } else {
+                if (has_out) intra2_pass<T, false, true>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, false, false>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
             }
         }
 #pragma unroll
@@ -892,7 +951,7 @@ __global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
             for (int half = 0; half < 2; ++half) {
                 if (ids[half] < 0) continue;
                 bool flag;
-                const int v = L::value(best, half, a.thr, &flag);
+                const int v = L::value(best, half, thr, &flag);
                 a.scores[(size_t)q * a.n_seqs + ids[half]] = v;
                 if (flag) {
                     const int pos = atomicAdd(a.ovf_count, 1);

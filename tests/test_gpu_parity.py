@@ -171,6 +171,32 @@ def test_forced_overflow_recompute(swmi, orc, tier, route):
         db.close()
 
 
+@pytest.mark.parametrize("alpha,beta", [(2, 12), (28, 40), (29, 40)])
+def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
+    """The packed fp16 wave-per-pair kernel (every subject on the long list,
+    9,000 pairs) with queries of one, two and three passes of 64 x T columns:
+    the pass boundary is stored as true values and re-offset on the way in.
+    Subjects span several 64-row feeder blocks and 32-step frame periods;
+    alpha 29 flags every half (ceiling 0) and the recompute keeps it exact."""
+    rng = np.random.Generator(np.random.PCG64(400 + alpha))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 9000, 20, 0, 260, zero_every=97)
+    db = swmi.Database(res, off, 20, long_threshold=1)
+    try:
+        db.set_opts(tier=1)
+        for L in [5, 300, 1100, 2100]:
+            q = sd.random_residues(rng, L)
+            print(f"packed wave-per-pair alpha={alpha} qlen={L}", flush=True)
+            exp = orc.search(q, res, off, M, alpha, beta)
+            expect_equal(db.search(q, M, alpha, beta), exp, f"packed a={alpha} L={L}")
+            st = db.stats()
+            assert st["intra_pairs"] == 9000 and st["inter_cells"] == 0
+            if alpha > 28:      # every half flagged, empty subjects included (best 0 >= 0)
+                assert st["recomputed_pairs"] == 9000
+    finally:
+        db.close()
+
+
 def test_planted_homologs_exceed_narrow_tiers(swmi, orc):
     """Scores above 1920 (fp16 tier) and above 32767 (int16 tier) stay exact."""
     rng = np.random.Generator(np.random.PCG64(5))

@@ -298,3 +298,143 @@ def test_frame_model_rejects_the_unshifted_ceiling(orc):
     check_claim(orc, Q, S, M, 20, 30, frame_ceiling(1920, 20), "frame")
     with pytest.raises(AssertionError):
         check_claim(orc, Q, S, M, 20, 30, 1920, "frame")
+
+
+def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, init_out_shift=True):
+    """Row-frame fp16 arithmetic of the packed wave-per-pair kernel, replayed
+    step by step: `lanes` lanes of T query columns each (a pass covers
+    lanes * T columns), lane l computing subject row t - l at step t, H and F
+    of its last column handed to lane l+1 one step later, lane 0 fed from the
+    previous pass's boundary (stored as true values) or from true 0, the last
+    lane's outputs collected as true values for the next pass.  Values of the
+    row at lane l and step t sit at offset alpha * ((t mod rows) - l); every
+    carried value drops by rows * alpha at the end of each block of `rows`
+    steps.  Vectorised over pairs of equal shape (Q: (B, m), S: (B, n)).
+    init_out_shift=False plants a wrong initial offset of the outputs handed
+    on before step 0 (used by the negative control)."""
+    B, m = Q.shape
+    n = S.shape[1]
+    f16 = np.float16
+    a = min(alpha, 28)
+    b = min(beta, 2048)
+    nalpha, palpha, nu, rb = f16(-a), f16(a), f16(a - b), f16(-rows * a)
+    A = M.shape[0]
+    Mx = np.zeros((A + 1, A + 1), np.int64)
+    Mx[:A, :A] = M
+    PW = lanes * T
+    npass = (m + PW - 1) // PW
+    Qp = np.full((B, npass * PW), A, np.int64)
+    Qp[:, :m] = Q
+    nblk = (n + lanes - 1) // lanes
+    L = np.arange(lanes)
+    best_true = np.zeros(B, f16)
+    bound_h = bound_f = None         # true values per row from the previous pass
+    with np.errstate(over="ignore", invalid="ignore"):
+        for p in range(npass):
+            has_in, has_out = p > 0, p + 1 < npass
+            steps = nblk * lanes + lanes - 1 if has_out else n + lanes - 1
+            off0 = (-a * L).astype(f16)                           # (lanes,)
+            H = np.broadcast_to((off0 + nalpha)[:, None, None], (lanes, T, B)).astype(f16).copy()
+            E = np.broadcast_to(off0[:, None, None], (lanes, T, B)).astype(f16).copy()
+            fl = np.broadcast_to((off0 + palpha)[:, None], (lanes, B)).astype(f16).copy()
+            best = (best_true[None, :] + off0[:, None]).astype(f16)
+            hb_prev = np.broadcast_to((off0 + nalpha)[:, None], (lanes, B)).astype(f16).copy()
+            o = off0 + nalpha if init_out_shift else off0
+            hout = np.broadcast_to(o[:, None], (lanes, B)).astype(f16).copy()
+            fout = hout.copy()
+            rowcode = np.full((lanes, B), A, np.int64)
+            new_h = np.zeros((max(nblk, 1) * lanes, B), f16)
+            new_f = np.zeros((max(nblk, 1) * lanes, B), f16)
+            for t in range(steps):
+                # lane 0 takes row t from the feeder, lane l the previous step's lane l-1
+                fr = S[:, t] if t < n else np.full(B, A, np.int64)
+                conv = f16(a * (t % rows))
+                if has_in and t < n:
+                    fh = (bound_h[t] + conv).astype(f16)
+                    ff = (bound_f[t] + conv).astype(f16)
+                else:
+                    fh = np.full(B, conv, f16)
+                    ff = fh.copy()
+                rowcode = np.concatenate([fr[None, :], rowcode[:-1]])
+                hin = np.concatenate([fh[None, :], hout[:-1]])
+                fin = np.concatenate([ff[None, :], fout[:-1]])
+                # one row per lane
+                hdiag = hb_prev
+                f = fin
+                for jj in range(T):
+                    col = p * PW + L * T + jj                          # (lanes,)
+                    s = (Mx[Qp[:, col].T, rowcode] + a).astype(f16)    # (lanes, B)
+                    hold = H[:, jj].copy()
+                    h = np.maximum(np.maximum((hdiag + s).astype(f16), E[:, jj]), f)
+                    tt = (h + nu).astype(f16)
+                    E[:, jj] = np.maximum(np.maximum(E[:, jj], tt), fl)
+                    f = (np.maximum(f, tt) + nalpha).astype(f16)
+                    H[:, jj] = h
+                    hdiag = hold
+                    best = np.maximum(best, h)
+                hout = H[:, T - 1].copy()
+                fout = f.copy()
+                hb_prev = hin
+                fl = (fl + palpha).astype(f16)
+                best = (best + palpha).astype(f16)
+                # the last lane finished row t - (lanes - 1): store it as a true value
+                r_done = t - (lanes - 1)
+                if has_out and 0 <= r_done < new_h.shape[0]:
+                    offw = f16(a * ((t % rows) - (lanes - 1)))
+                    new_h[r_done] = (hout[-1] - offw).astype(f16)
+                    new_f[r_done] = (fout[-1] - offw).astype(f16)
+                if (t + 1) % rows == 0:
+                    H = (H + rb).astype(f16)
+                    E = (E + rb).astype(f16)
+                    fl = (fl + rb).astype(f16)
+                    best = (best + rb).astype(f16)
+                    hb_prev = (hb_prev + rb).astype(f16)
+                    hout = (hout + rb).astype(f16)
+                    fout = (fout + rb).astype(f16)
+            oe = (a * ((steps % rows) - L)).astype(f16)
+            lane_best = (best - oe[:, None]).astype(f16)
+            best_true = lane_best.max(axis=0)
+            bound_h, bound_f = new_h, new_f
+    assert not np.isnan(best_true).any()
+    return best_true
+
+
+def check_intra2(orc, Q, S, M, alpha, beta, thr, **kw):
+    best = model_intra2_frame(Q, S, M, alpha, beta, **kw)
+    for x in range(Q.shape[0]):
+        exact = orc.sw_score(Q[x], S[x], M, alpha, beta)
+        flagged = not (float(best[x]) < thr)
+        assert flagged == (exact >= thr), (thr, exact, float(best[x]))
+        if not flagged:
+            assert int(best[x]) == exact, (thr, exact, float(best[x]))
+
+
+@pytest.mark.parametrize("thr", [1920, 300, 20])
+def test_intra2_row_frame_schedule(orc, thr):
+    """Packed wave-per-pair schedule with 8 lanes of T = 2 columns (passes of
+    16 columns): one to three passes, subjects spanning several 32-step
+    periods and several blocks of lanes, penalties across the alpha range."""
+    rng = np.random.Generator(np.random.PCG64(thr + 5))
+    A = 20
+    M = rng.integers(-4, 12, size=(A, A)).astype(np.int8)
+    for m, n in [(5, 40), (16, 70), (37, 90)]:
+        Q = rng.integers(0, A, size=(12, m)).astype(np.uint8)
+        S = rng.integers(0, A, size=(12, n)).astype(np.uint8)
+        S[:3, 10:10 + min(m, 30)] = Q[:3, :min(m, 30)]        # some high scores
+        for alpha, beta in [(2, 12), (1, 3), (28, 40)]:
+            c = frame_ceiling(thr, alpha)
+            check_intra2(orc, Q, S, M, alpha, beta, c, T=2, lanes=8)
+
+
+def test_intra2_model_rejects_a_wrong_initial_offset(orc):
+    """Negative control: outputs handed on before step 0 at the step-0 offset
+    instead of one step earlier leave lanes starting from a true value of
+    alpha, and unflagged scores come out too high."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    A = 20
+    M = rng.integers(-4, 12, size=(A, A)).astype(np.int8)
+    Q = rng.integers(0, A, size=(12, 20)).astype(np.uint8)
+    S = rng.integers(0, A, size=(12, 50)).astype(np.uint8)
+    check_intra2(orc, Q, S, M, 2, 12, 1854, T=2, lanes=8)
+    with pytest.raises(AssertionError):
+        check_intra2(orc, Q, S, M, 2, 12, 1854, T=2, lanes=8, init_out_shift=False)
