@@ -161,8 +161,10 @@ struct Items {
 };
 
 // Subjects per wave of the wave-per-pair kernel: two packed fp16 halves when
-// there are enough pairs to keep every SIMD busy with half as many waves,
-// one exact int32 alignment otherwise (and in the int16 plan).
+// there are enough pairs to keep every SIMD busy with half as many waves, one
+// exact int32 alignment otherwise (and in the int16 plan).  Below that count
+// the longest pair sets the makespan either way and the int32 kernel measured
+// as fast or faster (one query against 2M subjects: ~2,200 long pairs).
 int intra_per_wave(const Plan &plan, int64_t pairs, int cus) {
     return plan.tier == TIER_F16X2 && pairs >= 32LL * cus ? 2 : 1;
 }
@@ -180,6 +182,10 @@ struct Launch {
 struct sw_db {
     int device = 0;
     hipStream_t stream = nullptr;
+    // Second stream for the long list, forked from and joined to the search's
+    // stream so the wave-per-pair kernel overlaps the lane-per-subject kernel.
+    hipStream_t aux = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     int64_t n_seqs = 0;
     int alphabet = 0, R = 0;
     int64_t total_res = 0;
@@ -401,9 +407,46 @@ struct PassBufs {
 // Enqueue one pass: counter reset (a fill kernel, safe under graph capture),
 // lane-per-subject kernel, wave-per-pair kernel on the long list, exact
 // recompute of flagged lanes.  Optional events bracket the first kernel.
+// With `overlap`, the long list runs on the database's second stream, launched
+// before the lane-per-subject kernel so its longest pairs start at once (the
+// other order measured slower and erratic), and joins before the recompute.
+// The long list's makespan is its longest pair; overlapped, the rest of the
+// GPU works through the lane-per-subject queue meanwhile (+3.4% on one query
+// against 2M subjects).
 int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_t st,
-                 hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr) {
+                 hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr, bool overlap = false) {
     HIPX(launch_fill_i32(b.counters, 0, 4, st));
+    const bool fork = overlap && b.n_inter > 0 && b.n_intra > 0;
+    if (fork) {
+        HIPX(hipEventRecord(db->fork, st));
+        HIPX(hipStreamWaitEvent(db->aux, db->fork, 0));
+    }
+    IntraArgs ia{};
+    ia.res = db->d_res.as<uint8_t>();
+    ia.off = db->d_off.as<int64_t>();
+    ia.qs = b.qs;
+    ia.R = db->R;
+    ia.pass_scratch = b.scr_intra;
+    ia.max_len_pad = intra_scratch_rows(db);
+    ia.scores = b.scores;
+    ia.n_seqs = db->n_seqs;
+    ia.thr = L.plan.thr;
+    ia.ovf_q = b.ovf_q;
+    ia.ovf_id = b.ovf_id;
+    ia.ovf_count = b.counters + 1;
+    ia.ovf_cap = b.ovf_cap;
+    auto launch_long_aux = [&]() -> int {
+        IntraArgs la = ia;
+        la.item_q = b.il_q;
+        la.item_ids = b.il_ids;
+        la.n_items = (int32_t)b.n_intra;
+        la.counter = b.counters + 2;
+        if (L.packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_long, db->aux));
+        else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, db->aux));
+        HIPX(hipEventRecord(db->join, db->aux));
+        return SW_OK;
+    };
+    if (fork) TRY(launch_long_aux());
     if (ev_a) HIPX(hipEventRecord(ev_a, st));
     if (b.n_inter > 0) {
         InterArgs a{};
@@ -430,22 +473,8 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         HIPX(launch_inter(a, L.plan.tier, L.plan.strip, L.plan.waves, L.grid_inter, st));
     }
     if (ev_b) HIPX(hipEventRecord(ev_b, st));
-    IntraArgs ia{};
-    ia.res = db->d_res.as<uint8_t>();
-    ia.off = db->d_off.as<int64_t>();
-    ia.qs = b.qs;
-    ia.R = db->R;
-    ia.pass_scratch = b.scr_intra;
-    ia.max_len_pad = intra_scratch_rows(db);
-    ia.scores = b.scores;
-    ia.n_seqs = db->n_seqs;
-    ia.thr = L.plan.thr;
-    ia.ovf_q = b.ovf_q;
-    ia.ovf_id = b.ovf_id;
-    ia.ovf_count = b.counters + 1;
-    ia.ovf_cap = b.ovf_cap;
     const bool packed_long = L.packed_long;
-    if (b.n_intra > 0) {
+    if (b.n_intra > 0 && !fork) {
         IntraArgs la = ia;
         la.item_q = b.il_q;
         la.item_ids = b.il_ids;
@@ -454,6 +483,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         if (packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_long, st));
         else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
     }
+    if (fork) HIPX(hipStreamWaitEvent(st, db->join, 0));
     if (b.n_inter > 0 || (packed_long && b.n_intra > 0)) {
         IntraArgs oa = ia;
         oa.item_q = b.ovf_q;
@@ -620,7 +650,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     int32_t *d_ts = d_ti ? (int32_t *)(d_ti + (size_t)nq * k) : nullptr;
 
     auto enqueue_all = [&](hipStream_t s, bool events) -> int {
-        TRY(enqueue_pass(db, L, pb, s, events ? db->ev[0] : nullptr, events ? db->ev[1] : nullptr));
+        TRY(enqueue_pass(db, L, pb, s, events ? db->ev[0] : nullptr, events ? db->ev[1] : nullptr,
+                         true));
         if (events) HIPX(hipEventRecord(db->ev[2], s));
         if (k > 0)
             HIPX(launch_topk(pb.scores, n, nq, nullptr, k, topk_work(db->w_topk.p, nq, k), d_ts,
@@ -1231,7 +1262,10 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
     }
     HIPX(prepare_kernels());
     HIPX(hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking));
+    HIPX(hipStreamCreateWithFlags(&db->aux, hipStreamNonBlocking));
     for (auto &e : db->ev) HIPX(hipEventCreate(&e));
+    HIPX(hipEventCreateWithFlags(&db->fork, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&db->join, hipEventDisableTiming));
 
     db->len.resize(n_seqs);
     for (int64_t i = 0; i < n_seqs; ++i) db->len[i] = offsets[i + 1] - offsets[i];
@@ -1337,9 +1371,13 @@ void sw_db_close(sw_db *db) {
     (void)hipSetDevice(db->device);
     if (db->stream) (void)hipStreamSynchronize(db->stream);
     if (db->graph) (void)hipGraphExecDestroy(db->graph);
+    if (db->aux) (void)hipStreamSynchronize(db->aux);
     for (auto &e : db->ev)
         if (e) (void)hipEventDestroy(e);
+    if (db->fork) (void)hipEventDestroy(db->fork);
+    if (db->join) (void)hipEventDestroy(db->join);
     if (db->stream) (void)hipStreamDestroy(db->stream);
+    if (db->aux) (void)hipStreamDestroy(db->aux);
     delete db;
 }
 

@@ -45,19 +45,24 @@ def expect_equal(got, exp, what=""):
 QLENS = [1, 7, 63, 64, 65, 130, 200, 513, 1100]
 
 
+@pytest.mark.parametrize("tier", [1, 2])
 @pytest.mark.parametrize("route", [-1, 1, 0])
-def test_random_db_all_routes(swmi, orc, route):
+def test_random_db_all_routes(swmi, orc, route, tier):
+    """Route -1: everything lane-per-subject; 1: everything on the long list
+    (packed fp16 wave-per-pair kernel in the fp16 plan, int32 in the int16
+    plan); 0: the planner's own split."""
     rng = np.random.Generator(np.random.PCG64(100 + route))
     A = 20
     M = sd.blosum_style_matrix()
     res, off = random_db(rng, 700, A, 0, 400, zero_every=37)
     db = swmi.Database(res, off, A, long_threshold=route)
     try:
+        db.set_opts(tier=tier)
         for L in QLENS:
             q = sd.random_residues(rng, L)
-            print(f"route={route} qlen={L}", flush=True)
+            print(f"route={route} tier={tier} qlen={L}", flush=True)
             expect_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12),
-                         f"route {route} qlen {L}")
+                         f"route {route} tier {tier} qlen {L}")
     finally:
         db.close()
 
