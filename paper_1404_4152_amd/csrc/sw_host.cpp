@@ -298,8 +298,9 @@ int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> 
     if (!db->fixed_cut) {
         double strips = 0, max_strips = 1;
         for (int32_t m : mpad) {
-            strips += m / plan.strip;
-            max_strips = std::max<double>(max_strips, m / plan.strip);
+            const double ms = (m + plan.strip - 1) / plan.strip;
+            strips += ms;
+            max_strips = std::max<double>(max_strips, ms);
         }
         const double rows = (double)db->inter_padded_rows / kGroup;
         const double share = strips * rows / std::max(resident_waves, 1) / max_strips;
@@ -334,7 +335,7 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     v.reserve((size_t)slots.size() * (size_t)std::max<int64_t>(b1 - b0, 0));
     for (size_t x = 0; x < slots.size(); ++x) {
         const int32_t s = slots[x];
-        const int64_t strips = mpad[x] / plan.strip;
+        const int64_t strips = (mpad[x] + plan.strip - 1) / plan.strip;
         for (int64_t bk = b0; bk < b1; ++bk) {
             if (stride > 1 && (bk % stride) != 0) continue;
             const int last = (int)std::min<int64_t>(db->n_groups, (bk + 1) * W) - 1;
@@ -725,7 +726,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     int64_t inter_rows = 0;
     for (int64_t g = 0; g < g_cut; ++g) inter_rows += (int64_t)db->grp_rows[g] * kGroup;
     for (int32_t q = 0; q < nq; ++q)
-        padded += (int64_t)mpad[q] * inter_rows + round_up(qlen[q], 64LL * L.Ti) * long_res;
+        padded += round_up((int64_t)mpad[q], (int64_t)plan.strip) * inter_rows +
+                  round_up(qlen[q], 64LL * L.Ti) * long_res;
     s.padded_cells = padded;
     s.inter_cells = sum_qlen * db->grp_res_prefix[g_cut];
     s.recomputed_pairs = ctr_h[1];

@@ -16,8 +16,9 @@ constexpr int kWave = 64;
 constexpr int kGroup = 2 * kWave;
 // Rows per residue/boundary chunk of the lane-per-subject kernel.
 constexpr int kChunk = 4;
-// Query profiles are padded to a multiple of this many columns.
-constexpr int kQPad = 64;
+// Query profiles are padded to a multiple of this many columns (a strip of 64
+// runs past the end of a profile padded to 32; those columns score 0).
+constexpr int kQPad = 32;
 
 // Exactness ceilings of the narrow tiers (see sw_kernels.hip for the proofs).
 constexpr int kThrF16 = 1920;    // fp16 holds every integer in [-2048, 2048]
@@ -43,7 +44,7 @@ enum Tier : int { TIER_F16X2 = 1, TIER_I16X2 = 2 };
 // of the score matrix.
 struct QuerySet {
     const int8_t *const *qp;
-    const int32_t *mpad;     // padded length (multiple of kQPad)
+    const int32_t *mpad;     // padded length (multiple of kQPad, even)
     const int32_t *qlen;     // real length
     const int32_t *gap;      // alpha, beta of slot q at gap[2q], gap[2q+1]
 };

@@ -467,7 +467,7 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
         const bool active = g < a.n_groups;
         const int rows = active ? a.grp_rows[g] : 0;
         const int mp = a.qs.mpad[q];
-        const int nstrips = mp / T;
+        const int nstrips = (mp + T - 1) / T;   // the last strip may run past mp (scores 0)
         const int8_t *qp = a.qs.qp[q];
         const uint16_t *codes = a.codes + (active ? a.grp_base[g] : 0) + lane * 4;
         V best = L::zero();
@@ -476,8 +476,10 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
             __syncthreads();   // previous table no longer read; s_item consumed
             for (int e = threadIdx.x; e < R * (T / 2); e += W * 64) {
                 const int r = e / (T / 2), jj = e - r * (T / 2);
-                const int8_t *src = qp + (size_t)r * mp + k * T + 2 * jj;
-                stage[e] = (uint32_t)L::enc(src[0] + bias) | ((uint32_t)L::enc(src[1] + bias) << 16);
+                const int col = k * T + 2 * jj;    // mp is even, so col < mp covers col + 1
+                const int8_t *src = qp + (size_t)r * mp + col;
+                const int s0 = col < mp ? src[0] : 0, s1 = col < mp ? src[1] : 0;
+                stage[e] = (uint32_t)L::enc(s0 + bias) | ((uint32_t)L::enc(s1 + bias) << 16);
             }
             __syncthreads();
             for (int e = threadIdx.x; e < RR * (T / 2); e += W * 64) {
