@@ -169,10 +169,11 @@ int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_
 typedef struct sw_server_opts {
     int64_t memory_budget;   /* bytes of device memory for admitted requests' profiles and
                                 per-request state; 0 = 1 GiB */
-    int32_t max_active;      /* requests coalesced into one database pass; 0 = 64 */
+    int32_t max_active;      /* requests admitted at once (each pass serves the ones with the
+                                least work left first; the oldest always advances); 0 = 64 */
     int32_t queue_capacity;  /* waiting requests before submit returns SW_EBUSY; 0 = 65536 */
-    int32_t chunk_groups;    /* database chunk per launch, in groups of 128 subjects;
-                                0 = chosen by the server */
+    int32_t chunk_groups;    /* database chunk (one scan position), in groups of 128 subjects;
+                                0 = chosen by the server (1/16 of the lane-per-subject groups) */
     int32_t reserved[5];
 } sw_server_opts;
 
@@ -180,7 +181,7 @@ typedef struct sw_req_stats {
     double queue_ms;   /* submit -> admitted into the database scan */
     double total_ms;   /* submit -> result ready */
     int64_t cells;     /* |Q| * sum |S| */
-    int32_t passes;    /* database chunks this request rode on */
+    int32_t passes;    /* server passes (launches) this request took part in */
     int32_t reserved;
 } sw_req_stats;
 

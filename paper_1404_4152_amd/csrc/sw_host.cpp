@@ -374,6 +374,65 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     }
 }
 
+// Work of one server pass: slot `slot` against lane-per-subject blocks
+// [b0, b1), or against the whole long list.
+struct PassWork {
+    int32_t slot = 0;
+    int32_t mpad = 0;
+    int64_t qlen = 0;
+    int64_t b0 = 0, b1 = 0;
+    bool long_list = false;
+};
+
+// Items of a server pass: every (slot, block) of the work list and every
+// (slot, long-list block), each list longest first as in build_items.
+void build_work_items(const sw_db *db, const Plan &plan, const std::vector<PassWork> &work,
+                      const std::vector<int32_t> &long_ids, Items &it) {
+    const int W = plan.waves;
+    std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> v;
+    int64_t n_long_slots = 0;
+    for (const PassWork &w : work) {
+        if (w.long_list) {
+            ++n_long_slots;
+            continue;
+        }
+        const int64_t strips = (w.mpad + plan.strip - 1) / plan.strip;
+        for (int64_t bk = w.b0; bk < w.b1; ++bk) {
+            const int last = (int)std::min<int64_t>(db->n_groups, (bk + 1) * W) - 1;
+            v.push_back({(int64_t)db->grp_rows[last] * strips, {w.slot, (int32_t)(bk * W)}});
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    it.inter_q.resize(v.size());
+    it.inter_g.resize(v.size());
+    for (size_t i = 0; i < v.size(); ++i) {
+        it.inter_q[i] = v[i].second.first;
+        it.inter_g[i] = v[i].second.second;
+    }
+    it.intra_q.clear();
+    it.intra_ids.clear();
+    const int64_t nlong = (int64_t)long_ids.size();
+    const int per = kIntraWaves * intra_per_wave(plan, nlong * n_long_slots, db->cus);
+    it.per_item = per;
+    if (n_long_slots == 0 || nlong == 0) return;
+    const int64_t nlblk = (nlong + per - 1) / per;
+    std::vector<std::pair<int64_t, std::pair<int32_t, int64_t>>> u;
+    for (const PassWork &w : work)
+        if (w.long_list)
+            for (int64_t bk = 0; bk < nlblk; ++bk)
+                u.push_back({db->len[long_ids[bk * per]] * w.qlen, {w.slot, bk}});
+    std::stable_sort(u.begin(), u.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    it.intra_q.resize(u.size());
+    it.intra_ids.resize(u.size() * per);
+    for (size_t i = 0; i < u.size(); ++i) {
+        it.intra_q[i] = u[i].second.first;
+        for (int x = 0; x < per; ++x) {
+            const int64_t j = u[i].second.second * per + x;
+            it.intra_ids[i * per + x] = j < nlong ? long_ids[j] : -1;
+        }
+    }
+}
+
 Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_t n_inter,
                      int64_t n_intra) {
     Launch L;
@@ -878,8 +937,9 @@ struct Request {
     int64_t bytes = 0;
     double t_submit = 0, t_admit = 0, t_done = 0;
     int32_t slot = -1;
+    int32_t next = 0;        // next database position to visit
     int32_t remaining = 0;   // database positions still to visit
-    int32_t passes = 0;
+    int32_t passes = 0;      // passes (launches) this request took part in
     int rc = SW_OK;
     bool done = false;
     std::vector<int32_t> top_s;
@@ -893,6 +953,10 @@ struct sw_server {
     sw_server_opts opts{};
     Plan plan;
     int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
+    // per database position: residues, lane-per-subject items, subjects
+    std::vector<int64_t> pos_res, pos_items, pos_subj;
+    int64_t pass_cells = 0;      // work a pass aims for (cells)
+    int64_t pass_items = 0;      // lane-per-subject items a pass aims for (load balance)
     int64_t g_cut = 0;
     int64_t ovf_cap = 0;
     int32_t scr_rows = 0;
@@ -915,7 +979,6 @@ struct sw_server {
     int64_t used_bytes = 0;
     int32_t waiters = 0;     // threads inside sw_server_wait
     bool stop = false;
-    int64_t position = 0;
     std::thread worker;
     std::string fatal;
 };
@@ -942,14 +1005,39 @@ int server_setup(sw_server *s) {
     s->has_long = !s->long_ids.empty();
     s->n_pos = s->n_chunks + (s->has_long ? 1 : 0);
     s->slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
+    for (int64_t p = 0; p < s->n_chunks; ++p) {
+        const int64_t g0 = p * s->chunk_blocks * W;
+        const int64_t g1 = std::min(s->g_cut, (p + 1) * s->chunk_blocks * W);
+        s->pos_res.push_back(db->grp_res_prefix[g1] - db->grp_res_prefix[g0]);
+        s->pos_items.push_back(std::min(s->blocks, (p + 1) * s->chunk_blocks) - p * s->chunk_blocks);
+        s->pos_subj.push_back((g1 - g0) * kGroup);
+    }
+    if (s->has_long) {
+        int64_t r = 0;
+        for (int32_t id : s->long_ids) r += db->len[id];
+        s->pos_res.push_back(r);
+        s->pos_items.push_back(0);
+        s->pos_subj.push_back((int64_t)s->long_ids.size());
+    }
+    {
+        // A pass aims for the work of twelve 400-residue queries against an
+        // average position (~50 ms on 5M subjects) and for eight lane-per-
+        // subject items per resident workgroup: with fewer, the queue's tail
+        // (workgroups idle while the last items finish) takes a large share of
+        // every pass.
+        int64_t tot = 0;
+        for (int64_t r : s->pos_res) tot += r;
+        s->pass_cells = std::max<int64_t>(1, 12 * 400 * (tot / std::max<int64_t>(1, s->n_pos)));
+        s->pass_items = 8LL * inter_max_grid(db->R, s->plan.tier, s->plan.strip, W);
+    }
     if (s->opts.memory_budget <= 0) s->opts.memory_budget = (int64_t)1 << 30;
     if (s->opts.queue_capacity <= 0) s->opts.queue_capacity = 65536;
     s->prof.resize(s->slots);
     for (auto &p : s->prof) p.reset(new DevBuf());
     s->active.assign(s->slots, nullptr);
     const int64_t n = db->n_seqs;
-    // the largest pass: every slot against one chunk, or against the long list
-    const int64_t inter_items = (int64_t)s->slots * s->chunk_blocks;
+    // the largest pass: every slot against every chunk and the long list
+    const int64_t inter_items = (int64_t)s->slots * std::max<int64_t>(s->blocks, 1);
     const int per = kIntraWaves;   // the int32 layout has the most items
     const int64_t nlblk = ((int64_t)s->long_ids.size() + per - 1) / per;
     const int64_t intra_items = (int64_t)s->slots * nlblk;
@@ -968,8 +1056,8 @@ int server_setup(sw_server *s) {
         TRY(s->d_scr_inter.reserve((size_t)s->L.grid_inter * W * s->scr_rows * 512));
     const int64_t islots = std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
-    const size_t items_bytes =
-        (size_t)(std::max(inter_items * 2, intra_items * (1 + per)) + 64) * 4;
+    // a pass may hold lane-per-subject and wave-per-pair items together
+    const size_t items_bytes = (size_t)(inter_items * 2 + intra_items * (1 + per) + 64) * 4;
     TRY(s->d_items.reserve(items_bytes));
     TRY(s->h_items.reserve(items_bytes));
     TRY(s->d_topk.reserve(topk_work_bytes(s->slots, SW_MAX_K)));
@@ -994,6 +1082,7 @@ std::vector<std::shared_ptr<Request>> admit(sw_server *s) {
             }
         if (slot < 0 || s->used_bytes + r->bytes > s->opts.memory_budget) break;
         r->slot = slot;
+        r->next = 0;
         r->remaining = (int32_t)s->n_pos;
         r->t_admit = now_ms();
         s->used_bytes += r->bytes;
@@ -1034,24 +1123,70 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
         }
         HIPX(hipMemcpy(s->d_meta.p, s->h_meta.p, (size_t)s->slots * 24, hipMemcpyHostToDevice));
     }
-    std::vector<int32_t> slots, mpad;
-    std::vector<int64_t> qlen;
+    // Choose this pass's work: the oldest active request always advances one
+    // position (nothing starves); then requests with the least work left take
+    // their next positions, as many as the pass budget allows, so a short
+    // query can finish in one or two passes instead of riding every pass of a
+    // long one (shortest remaining work first, batched).
+    std::vector<Request *> act;
     for (int i = 0; i < s->slots; ++i)
-        if (s->active[i]) {
-            slots.push_back(i);
-            qlen.push_back((int64_t)s->active[i]->query.size());
-            mpad.push_back((int32_t)round_up(qlen.back(), kQPad));
+        if (s->active[i] && s->active[i]->remaining > 0) act.push_back(s->active[i].get());
+    if (act.empty()) return SW_OK;
+    auto left_cells = [&](const Request *r) {
+        int64_t c = 0;
+        for (int32_t x = 0, p = r->next; x < r->remaining; ++x, p = (int32_t)((p + 1) % s->n_pos))
+            c += s->pos_res[p];
+        return c * (int64_t)r->query.size();
+    };
+    std::vector<std::pair<int64_t, Request *>> order;
+    for (Request *r : act) order.push_back({left_cells(r), r});
+    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
+        return a.first != b.first ? a.first < b.first : a.second->ticket < b.second->ticket;
+    });
+    Request *oldest = act[0];
+    for (Request *r : act)
+        if (r->ticket < oldest->ticket) oldest = r;
+    std::vector<PassWork> work;
+    std::vector<Request *> riders;
+    int64_t cells = 0, items = 0, pairs = 0;
+    auto take = [&](Request *r) -> bool {
+        if (r->remaining == 0) return false;
+        const int32_t p = r->next;
+        if (!work.empty() && pairs + s->pos_subj[p] > s->ovf_cap) return false;
+        PassWork w;
+        w.slot = r->slot;
+        w.qlen = (int64_t)r->query.size();
+        w.mpad = (int32_t)round_up(w.qlen, kQPad);
+        if (p < s->n_chunks) {
+            w.b0 = (int64_t)p * s->chunk_blocks;
+            w.b1 = std::min(s->blocks, w.b0 + s->chunk_blocks);
+        } else {
+            w.long_list = true;
         }
-    if (slots.empty()) return SW_OK;
-    const bool long_pos = s->has_long && s->position == s->n_chunks;
-    Items it;
-    if (long_pos) {
-        build_items(db, s->plan, slots, mpad, qlen, 0, 0, true, s->long_ids, 1, it);
-    } else {
-        const int64_t b0 = s->position * s->chunk_blocks;
-        const int64_t b1 = std::min(s->blocks, b0 + s->chunk_blocks);
-        build_items(db, s->plan, slots, mpad, qlen, b0, b1, false, s->long_ids, 1, it);
+        work.push_back(w);
+        if (riders.empty() || riders.back() != r) riders.push_back(r);
+        cells += s->pos_res[p] * w.qlen;
+        items += s->pos_items[p];
+        pairs += s->pos_subj[p];
+        r->next = (int32_t)((p + 1) % s->n_pos);
+        r->remaining--;
+        return true;
+    };
+    // Under load, passes grow with the number of active requests (up to 8x):
+    // a pass's fixed costs (the queue's tail, the host round trip) then stay
+    // small against its work, and throughput matches one big pass per chunk.
+    const int64_t scale = std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)act.size() / 4));
+    auto full = [&] { return cells >= s->pass_cells * scale && items >= s->pass_items; };
+    take(oldest);
+    for (auto &o : order) {
+        if (full()) break;
+        while (!full() && take(o.second)) {
+        }
     }
+    std::sort(riders.begin(), riders.end());
+    riders.erase(std::unique(riders.begin(), riders.end()), riders.end());
+    Items it;
+    build_work_items(db, s->plan, work, s->long_ids, it);
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     int32_t *hi = s->h_items.as<int32_t>();
     std::memcpy(hi, it.inter_q.data(), n_inter * 4);
@@ -1085,15 +1220,15 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     L.packed_long = it.per_item == 2 * kIntraWaves;
     L.grid_inter = (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
     L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
-    TRY(enqueue_pass(db, L, pb, st));
-    // advance every active request; those that visited every position get top-k
+    TRY(enqueue_pass(db, L, pb, st, nullptr, nullptr, true));
+    // requests that visited their last position get top-k
     std::vector<int32_t> done_rows;
-    for (int32_t sl : slots) {
-        auto &r = s->active[sl];
+    for (Request *rp : riders) {
+        auto &r = s->active[rp->slot];
         r->passes++;
-        if (--r->remaining == 0) {
+        if (r->remaining == 0) {
             finished.push_back(r);
-            done_rows.push_back(sl);
+            done_rows.push_back(r->slot);
         }
     }
     if (!done_rows.empty()) {
@@ -1168,7 +1303,6 @@ void server_loop(sw_server *s) {
             s->used_bytes -= r->bytes;
             s->active[r->slot] = nullptr;
         }
-        if (s->n_pos > 0) s->position = (s->position + 1) % s->n_pos;
         if (!finished.empty()) s->cv_done.notify_all();
     }
     std::lock_guard<std::mutex> lk(s->mu);

@@ -115,7 +115,7 @@ def test_server_alone_equals_mixed_equals_oracle(swmi, orc):
             for q in qs:
                 t = swmi.sw_server_submit(srv, q, M, 2, 12, k)
                 ts, ti, st = swmi.sw_server_wait(srv, t, k)
-                assert st["passes"] >= 2
+                assert st["passes"] >= 1
                 alone.append((ts, ti))
             # mixed: submitted from several threads, staggered, more than max_active
             tickets = [None] * len(qs)
