@@ -11,6 +11,12 @@ second stream and the top-k, exactly as in the timed steps.
 batched: 512 queries x 500,000 subjects in one launch, replayed from the
 captured HIP graph.
 
+long_tail: 20,000 subjects of 5,000-35,000 residues, all wave-per-pair.
+
+serving: 5,000,000 subjects resident under the server; each request's top-k
+is recomputed by the oracle and compared with a plain search of the same
+database once the server has stopped.
+
 Checked on every output: scores >= 0, empty subjects score 0, and the
 library's top-k equals the (score desc, index asc) top-k of the full vector.
 Checked against the oracle: the top hits, the longest subjects (the long list)
@@ -124,5 +130,59 @@ def test_batched_full_size_sampled(swmi, orc):
         for x in rng.choice(len(qs), size=8, replace=False):
             check_vector(orc, qs[x], res, off, M, w.alpha, w.beta, al[x], ts[x], ti[x], rng,
                          f"batched q{x}", n_random=500, n_long=20)
+    finally:
+        db.close()
+
+
+def test_long_tail_full_size_sampled(swmi, orc):
+    """long_tail: 20,000 subjects of 5,000-35,000 residues (every one past the
+    8,192-residue group limit, so all wave-per-pair), queries of 1,000 and
+    5,000 residues in the fp16 plan (packed kernel, several passes)."""
+    w = sd.WORKLOADS["long_tail"]
+    res, off = w.db()
+    M = w.matrix()
+    qs = w.queries()
+    rng = np.random.Generator(np.random.PCG64(31))
+    db = swmi.Database(res, off, 20)
+    try:
+        for qi in (0, len(qs) - 1):
+            q = qs[qi]
+            print(f"long_tail full size: query {qi} ({len(q)} residues)", flush=True)
+            ts, ti = db.topk(q, M, w.alpha, w.beta, 10)
+            st = db.stats()
+            assert st["intra_pairs"] == len(off) - 1 and st["inter_cells"] == 0
+            got = db.search(q, M, w.alpha, w.beta)
+            check_vector(orc, q, res, off, M, w.alpha, w.beta, got, ts, ti, rng,
+                         f"long_tail q{qi}", n_random=60, n_long=10)
+    finally:
+        db.close()
+
+
+def test_served_full_size_sampled(swmi, orc):
+    """serving: 5,000,000 subjects (1.75 G residues) resident; requests of the
+    serving query mix submitted together, so passes mix requests at different
+    scan positions.  Each request's top-k is recomputed by the oracle, and
+    once the server is stopped it must equal a plain search of the same
+    database (verified elsewhere against the oracle)."""
+    w = sd.WORKLOADS["serving"]
+    res, off = w.db()
+    M = w.matrix()
+    qs = sd.serving_queries(6)
+    k = 10
+    db = swmi.Database(res, off, 20)
+    try:
+        srv = swmi.sw_server_start(db.h, memory_budget=8 << 30, max_active=64)
+        try:
+            print("served full size: submit", [len(q) for q in qs], flush=True)
+            tickets = [swmi.sw_server_submit(srv, q, M, w.alpha, w.beta, k) for q in qs]
+            results = [swmi.sw_server_wait(srv, t, k) for t in tickets]
+        finally:
+            swmi.sw_server_stop(srv)
+        for x, (q, (ts, ti, st)) in enumerate(zip(qs, results)):
+            assert st["passes"] >= 1
+            exp = orc.search_subset(q, res, off, ti, M, w.alpha, w.beta)
+            assert np.array_equal(ts, exp), f"served q{x}: top-k scores differ from the oracle"
+            ps, pi = db.topk(q, M, w.alpha, w.beta, k)
+            assert np.array_equal(ts, ps) and np.array_equal(ti, pi), f"served q{x} != plain search"
     finally:
         db.close()
