@@ -141,6 +141,26 @@ def test_fp16_row_frame_alpha_range(swmi, orc, alpha):
             db.close()
 
 
+@pytest.mark.parametrize("route", [-1, 1])
+def test_very_long_query(swmi, orc, route):
+    """A 30,000-residue query: 938 strips of the lane-per-subject kernel (the
+    boundary buffer reused strip after strip) or 30 passes of the wave-per-pair
+    kernel, against subjects of up to 300 residues."""
+    rng = np.random.Generator(np.random.PCG64(600 + route))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 3000, 20, 0, 300, zero_every=101)
+    q = sd.random_residues(rng, 30_000)
+    n7 = min(200, int(off[8] - off[7]))
+    q[12_000:12_000 + n7] = res[off[7]:off[7] + n7]      # a high-scoring hit mid-query
+    db = swmi.Database(res, off, 20, long_threshold=route)
+    try:
+        print(f"very long query route={route}", flush=True)
+        expect_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12),
+                     f"30k query route {route}")
+    finally:
+        db.close()
+
+
 def test_asymmetric_matrix_orientation(swmi, orc):
     M = np.array([[0, 5], [-3, 0]], np.int8)
     res, off = sd.pack_sequences([np.array([1], np.uint8), np.array([0], np.uint8)])
