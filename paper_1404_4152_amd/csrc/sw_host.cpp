@@ -35,6 +35,7 @@
 
 #include "../../include/swmi.h"
 #include "sw_internal.h"
+#include "sw_sched.h"
 
 using namespace swmi;
 
@@ -953,8 +954,7 @@ struct sw_server {
     sw_server_opts opts{};
     Plan plan;
     int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
-    // per database position: residues, lane-per-subject items, subjects
-    std::vector<int64_t> pos_res, pos_items, pos_subj;
+    std::vector<SchedPos> pos;   // per database position: residues, items, subjects
     int64_t pass_cells = 0;      // work a pass aims for (cells)
     int64_t pass_items = 0;      // lane-per-subject items a pass aims for (load balance)
     int64_t g_cut = 0;
@@ -1008,16 +1008,17 @@ int server_setup(sw_server *s) {
     for (int64_t p = 0; p < s->n_chunks; ++p) {
         const int64_t g0 = p * s->chunk_blocks * W;
         const int64_t g1 = std::min(s->g_cut, (p + 1) * s->chunk_blocks * W);
-        s->pos_res.push_back(db->grp_res_prefix[g1] - db->grp_res_prefix[g0]);
-        s->pos_items.push_back(std::min(s->blocks, (p + 1) * s->chunk_blocks) - p * s->chunk_blocks);
-        s->pos_subj.push_back((g1 - g0) * kGroup);
+        SchedPos sp;
+        sp.res = db->grp_res_prefix[g1] - db->grp_res_prefix[g0];
+        sp.items = std::min(s->blocks, (p + 1) * s->chunk_blocks) - p * s->chunk_blocks;
+        sp.subj = (g1 - g0) * kGroup;
+        s->pos.push_back(sp);
     }
     if (s->has_long) {
-        int64_t r = 0;
-        for (int32_t id : s->long_ids) r += db->len[id];
-        s->pos_res.push_back(r);
-        s->pos_items.push_back(0);
-        s->pos_subj.push_back((int64_t)s->long_ids.size());
+        SchedPos sp;
+        for (int32_t id : s->long_ids) sp.res += db->len[id];
+        sp.subj = (int64_t)s->long_ids.size();
+        s->pos.push_back(sp);
     }
     {
         // A pass aims for the work of twelve 400-residue queries against an
@@ -1026,7 +1027,7 @@ int server_setup(sw_server *s) {
         // (workgroups idle while the last items finish) takes a large share of
         // every pass.
         int64_t tot = 0;
-        for (int64_t r : s->pos_res) tot += r;
+        for (const SchedPos &sp : s->pos) tot += sp.res;
         s->pass_cells = std::max<int64_t>(1, 12 * 400 * (tot / std::max<int64_t>(1, s->n_pos)));
         s->pass_items = 8LL * inter_max_grid(db->R, s->plan.tier, s->plan.strip, W);
     }
@@ -1123,65 +1124,38 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
         }
         HIPX(hipMemcpy(s->d_meta.p, s->h_meta.p, (size_t)s->slots * 24, hipMemcpyHostToDevice));
     }
-    // Choose this pass's work: the oldest active request always advances one
-    // position (nothing starves); then requests with the least work left take
-    // their next positions, as many as the pass budget allows, so a short
-    // query can finish in one or two passes instead of riding every pass of a
-    // long one (shortest remaining work first, batched).
+    // This pass's work (sw_sched.h): the oldest request advances one position,
+    // then shortest remaining work first, up to the pass budget.
     std::vector<Request *> act;
     for (int i = 0; i < s->slots; ++i)
         if (s->active[i] && s->active[i]->remaining > 0) act.push_back(s->active[i].get());
     if (act.empty()) return SW_OK;
-    auto left_cells = [&](const Request *r) {
-        int64_t c = 0;
-        for (int32_t x = 0, p = r->next; x < r->remaining; ++x, p = (int32_t)((p + 1) % s->n_pos))
-            c += s->pos_res[p];
-        return c * (int64_t)r->query.size();
-    };
-    std::vector<std::pair<int64_t, Request *>> order;
-    for (Request *r : act) order.push_back({left_cells(r), r});
-    std::stable_sort(order.begin(), order.end(), [](const auto &a, const auto &b) {
-        return a.first != b.first ? a.first < b.first : a.second->ticket < b.second->ticket;
-    });
-    Request *oldest = act[0];
-    for (Request *r : act)
-        if (r->ticket < oldest->ticket) oldest = r;
+    std::vector<SchedReq> sreq(act.size());
+    for (size_t i = 0; i < act.size(); ++i)
+        sreq[i] = SchedReq{act[i]->ticket, (int64_t)act[i]->query.size(), act[i]->next,
+                           act[i]->remaining};
+    std::vector<SchedTake> takes;
+    sched_plan_pass(sreq, s->pos, SchedBudget{s->pass_cells, s->pass_items, s->ovf_cap}, takes);
     std::vector<PassWork> work;
     std::vector<Request *> riders;
-    int64_t cells = 0, items = 0, pairs = 0;
-    auto take = [&](Request *r) -> bool {
-        if (r->remaining == 0) return false;
-        const int32_t p = r->next;
-        if (!work.empty() && pairs + s->pos_subj[p] > s->ovf_cap) return false;
+    for (const SchedTake &t : takes) {
+        Request *r = act[t.req];
         PassWork w;
         w.slot = r->slot;
         w.qlen = (int64_t)r->query.size();
         w.mpad = (int32_t)round_up(w.qlen, kQPad);
-        if (p < s->n_chunks) {
-            w.b0 = (int64_t)p * s->chunk_blocks;
+        if (t.pos < s->n_chunks) {
+            w.b0 = (int64_t)t.pos * s->chunk_blocks;
             w.b1 = std::min(s->blocks, w.b0 + s->chunk_blocks);
         } else {
             w.long_list = true;
         }
         work.push_back(w);
-        if (riders.empty() || riders.back() != r) riders.push_back(r);
-        cells += s->pos_res[p] * w.qlen;
-        items += s->pos_items[p];
-        pairs += s->pos_subj[p];
-        r->next = (int32_t)((p + 1) % s->n_pos);
-        r->remaining--;
-        return true;
-    };
-    // Under load, passes grow with the number of active requests (up to 8x):
-    // a pass's fixed costs (the queue's tail, the host round trip) then stay
-    // small against its work, and throughput matches one big pass per chunk.
-    const int64_t scale = std::min<int64_t>(16, std::max<int64_t>(1, (int64_t)act.size() / 4));
-    auto full = [&] { return cells >= s->pass_cells * scale && items >= s->pass_items; };
-    take(oldest);
-    for (auto &o : order) {
-        if (full()) break;
-        while (!full() && take(o.second)) {
-        }
+        riders.push_back(r);
+    }
+    for (size_t i = 0; i < act.size(); ++i) {
+        act[i]->next = sreq[i].next;
+        act[i]->remaining = sreq[i].remaining;
     }
     std::sort(riders.begin(), riders.end());
     riders.erase(std::unique(riders.begin(), riders.end()), riders.end());
