@@ -67,26 +67,14 @@ __device__ __forceinline__ uint32_t as_u(V v) { return __builtin_bit_cast(uint32
 // ---------------------------------------------------------------------------
 template <int TIER> struct Lane;
 
+// The fp16 tier's cell arithmetic is the row-frame form (FrameF16 and
+// FrameStrip below); this holds the encoding and the epilogue.
 template <> struct Lane<TIER_F16X2> {
     typedef h2 V;
-    V nalpha, nbeta;
-    __device__ Lane(int alpha, int beta) {
-        const _Float16 a = (_Float16)(float)(-alpha), b = (_Float16)(float)(-beta);
-        nalpha = V{a, a};
-        nbeta = V{b, b};
-    }
     static __device__ __forceinline__ V zero() { return V{(_Float16)0.0f, (_Float16)0.0f}; }
-    static __device__ __forceinline__ V max3(V a, V b, V c) {
-        return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
-    }
     static __device__ __forceinline__ uint16_t enc(int v) {
         return __builtin_bit_cast(uint16_t, (_Float16)(float)v);
     }
-    __device__ __forceinline__ V diag(V hd, V s) const { return hd + s; }
-    __device__ __forceinline__ V hmax(V hd, V e, V f) const { return max3(hd, e, f); }
-    __device__ __forceinline__ V open(V h) const { return h + nbeta; }
-    __device__ __forceinline__ V gap(V g, V t) const { return max3(g + nalpha, t, zero()); }
-    __device__ __forceinline__ V best2(V b, V h0, V h1) const { return max3(b, h0, h1); }
     // (score, flagged) of one half
     static __device__ __forceinline__ int value(V b, int half, int thr, bool *flag) {
         const float x = half ? (float)b.y : (float)b.x;
@@ -129,7 +117,8 @@ template <> struct Lane<TIER_I16X2> {
 __device__ __forceinline__ int div_r(int a, int magic) { return (a * magic) >> 16; }
 
 // ---------------------------------------------------------------------------
-// Lane-per-subject kernel.
+// Lane-per-subject kernel.  Strip evaluates the textbook form and serves the
+// int16 tier; the fp16 tier uses FrameStrip.
 // ---------------------------------------------------------------------------
 template <int T, int TIER>
 struct Strip {
