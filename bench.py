@@ -27,6 +27,7 @@ import json
 import os
 import sys
 import threading
+import tempfile
 import time
 
 import numpy as np
@@ -38,10 +39,10 @@ sys.path.insert(0, ROOT)
 CUS, CLOCK_GHZ = 256, 2.4
 PEAK_LANE_OPS = CUS * 64 * CLOCK_GHZ * 1e9          # 32-bit VALU lane-ops/s (39.3 T)
 PEAK_HALF_OPS = 2 * PEAK_LANE_OPS                    # packed 16-bit lane-ops/s (78.6 T)
-# VALU ops per cell of the fp16 row-frame form that the lane-per-subject
-# kernel evaluates: hdiag+s, max3 (H), h+(alpha-beta), max3 (E), max3+add (F),
-# and one max3 per two cells for the running best.
-OPS_PER_CELL = 6.5
+# VALU ops per cell of the fp16 frame form that the lane-per-subject kernel
+# evaluates: hdiag+s, max3 (H), h+(alpha-beta), max3 (E), max (F) plus one add
+# per four columns, and one max3 per two cells for the running best.
+OPS_PER_CELL = 5.75
 PEAK_GCUPS_F16X2 = PEAK_HALF_OPS / OPS_PER_CELL / 1e9
 
 
@@ -105,13 +106,19 @@ def run_plain(args, swmi, sd, torch):
     db = swmi.Database(res, off, 20, device=0)
     log(f"[bench] database opened (sorted, packed, uploaded) in {time.perf_counter() - t0:.1f}s")
     overridden = bool(args.tier or args.strip or args.waves)
+    tuned = None
     if overridden:
         db.set_opts(tier=args.tier, strip=args.strip, waves=args.waves)
     elif not args.no_autotune:
-        # plan per query-length bucket, timed on a sample of this database
+        # plan per query-length bucket, timed on this database; the table goes
+        # through a temporary cache file so that the JSON line can show it
         t0 = time.perf_counter()
-        swmi.sw_db_autotune(db.h, M, w.alpha, w.beta, [len(q) for q in queries], None)
-        log(f"[bench] autotuned plans in {time.perf_counter() - t0:.1f}s")
+        with tempfile.TemporaryDirectory() as td:
+            cache = os.path.join(td, "plans.json")
+            swmi.sw_db_autotune(db.h, M, w.alpha, w.beta, [len(q) for q in queries], cache)
+            tuned = [[e["bucket"], e["tier"], e["strip"], e["waves"], e["gcups"]]
+                     for e in json.load(open(cache))["entries"]]
+        log(f"[bench] autotuned plans in {time.perf_counter() - t0:.1f}s: {tuned}")
     # kernels, HIP events and torch's synchronisation share torch's current stream
     sptr = torch.cuda.current_stream().cuda_stream
     sum_q = sum(len(q) for q in queries)
@@ -151,6 +158,8 @@ def run_plain(args, swmi, sd, torch):
                    "alpha": w.alpha, "beta": w.beta,
                    "plans": sorted({(s["tier"], s["strip"], s["waves"]) for s in all_sts}),
                    "autotuned": not overridden and not args.no_autotune,
+                   # [query-length bucket (up to 64 << b residues), tier, strip, waves, GCUPS timed]
+                   "tuned_plans": tuned,
                    "parallelism": "single GPU"},
         "frac_of_f16x2_peak_gcups": round(gcups / PEAK_GCUPS_F16X2, 4),
         "kernel_gcups": round(cells_step * args.steps /
@@ -288,6 +297,9 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device three times (the reference "
+                         "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); sharding across GPUs is "
@@ -300,6 +312,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = 256 << 20
+        a = torch.empty(n // 4, dtype=torch.int32, device="cuda").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copied {n} bytes device to device, 3 times")
+        return
     out, (w, res, off, queries, M) = run_plain(args, swmi, sd, torch)
     if not args.no_batched and args.workload == "plain_scale":
         b = run_batched(args, swmi, sd, torch)

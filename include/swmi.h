@@ -158,8 +158,9 @@ int sw_db_search_batch(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_
                        const sw_scoring *sc, int32_t k, int32_t *top_scores, int64_t *top_idx,
                        int32_t *all_scores, void *hip_stream);
 
-/* Run the autotuner: time the candidate plans on a sample of this database for
- * the given query lengths and keep the fastest per query-length bucket.  If
+/* Run the autotuner: for each query-length bucket of the given lengths, time
+ * every candidate plan on a sample of this database's blocks, re-time the two
+ * fastest on the whole database (best of two runs) and keep the faster.  If
  * cache_path is non-NULL the table is read from / written to that JSON file. */
 int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,
                    const char *cache_path);

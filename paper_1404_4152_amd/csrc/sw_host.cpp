@@ -872,6 +872,27 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
     const int64_t stride =
         std::max<int64_t>(1, std::min<int64_t>(8, (db->n_groups / 4) / (16 * resident)));
     uint32_t lcg = 12345u;
+    // GCUPS of one plan: best of `reps` timed runs after one warm-up run (the
+    // first run warms caches and buffers; single runs of one plan vary by
+    // 10-20% with how the long list's kernel shares the chip).
+    auto time_plan = [&](const Plan &cand, const std::vector<uint8_t> &q, int64_t str,
+                         int reps, double *gcups) -> int {
+        sw_search_opts o{};
+        o.tier = cand.tier;
+        o.strip = cand.strip;
+        o.waves = cand.waves;
+        db->opts = o;
+        const int64_t off[2] = {0, (int64_t)q.size()};
+        double ms = 1e30;
+        for (int rep = 0; rep <= reps; ++rep) {
+            const int rc = run_search(db, 1, q.data(), off, sc, 0, nullptr, nullptr, nullptr,
+                                      nullptr, nullptr, str);
+            if (rc != SW_OK) return rc;
+            if (rep > 0) ms = std::min(ms, (double)db->last.inter_ms);
+        }
+        *gcups = (double)db->last.inter_cells / str / (ms * 1e6);
+        return SW_OK;
+    };
     for (int32_t x = 0; x < n_qlens; ++x) {
         const int64_t L = std::max(1, std::min(qlens[x], SW_MAX_LEN));
         const int b = qlen_bucket(L);
@@ -881,30 +902,35 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
             lcg = lcg * 1664525u + 1013904223u;
             c = (uint8_t)((lcg >> 16) % (uint32_t)db->alphabet);
         }
-        const int64_t off[2] = {0, L};
-        double best = -1;
-        Plan best_plan;
+        // Screen every candidate on the sampled blocks, then time the two best
+        // on the whole database and keep the faster.
+        std::vector<std::pair<double, Plan>> screened;
         for (const Plan &cand : kCandidates) {
             if (inter_lds_bytes(db->R, cand.strip) > 150 * 1024) continue;
-            sw_search_opts o{};
-            o.tier = cand.tier;
-            o.strip = cand.strip;
-            o.waves = cand.waves;
-            db->opts = o;
-            double ms = 1e30;
-            for (int rep = 0; rep < 2; ++rep) {   // the first run warms caches and buffers
-                int rc = run_search(db, 1, q.data(), off, sc, 0, nullptr, nullptr, nullptr, nullptr,
-                                    nullptr, stride);
+            double gc = 0;
+            const int rc = time_plan(cand, q, stride, 1, &gc);
+            if (rc != SW_OK) {
+                db->opts = saved;
+                return rc;
+            }
+            screened.push_back({gc, cand});
+        }
+        std::stable_sort(screened.begin(), screened.end(),
+                         [](const auto &x, const auto &y) { return x.first > y.first; });
+        double best = -1;
+        Plan best_plan = screened.empty() ? Plan{} : screened[0].second;
+        for (size_t i = 0; i < screened.size() && i < 2; ++i) {
+            double gc = screened[i].first;
+            if (stride > 1) {
+                const int rc = time_plan(screened[i].second, q, 1, 2, &gc);
                 if (rc != SW_OK) {
                     db->opts = saved;
                     return rc;
                 }
-                if (rep > 0) ms = db->last.inter_ms;
             }
-            const double gc = (double)db->last.inter_cells / stride / (ms * 1e6);
             if (gc > best) {
                 best = gc;
-                best_plan = cand;
+                best_plan = screened[i].second;
             }
         }
         db->tuned[b] = best_plan;

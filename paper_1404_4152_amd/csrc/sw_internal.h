@@ -23,17 +23,27 @@ constexpr int kQPad = 32;
 // Exactness ceilings of the narrow tiers (see sw_kernels.hip for the proofs).
 constexpr int kThrF16 = 1920;    // fp16 holds every integer in [-2048, 2048]
 constexpr int kThrI16 = 32767;   // saturating int16
-// The lane-per-subject fp16 tier keeps values offset by up to kFrameRows *
-// alpha (row frame, see sw_kernels.hip), so its ceiling for a query with gap
-// extension alpha is kThrF16 - (kFrameRows + 1) * alpha.  Above
-// kFrameMaxAlpha the planner prefers the int16 tier; above kFrameFlagAlpha
-// the fp16 tier flags every lane of the query for the exact recompute.
+// The fp16 kernels keep values in frames that move by alpha per row (see
+// sw_kernels.hip).  The packed wave-per-pair kernel offsets by up to
+// kFrameRows * alpha: ceiling kThrF16 - (kFrameRows + 1) * alpha, every lane
+// flagged above kFrameFlagAlpha.  The lane-per-subject kernel also offsets
+// the columns of each group of kFrameCols by alpha per column, up to
+// (kFrameRows + kFrameCols - 1) * alpha: ceiling
+// kThrF16 - (kFrameRows + kFrameCols) * alpha, every lane flagged above
+// kLaneFlagAlpha.  Above kFrameMaxAlpha the planner prefers the int16 tier.
 constexpr int kFrameRows = 32;
+constexpr int kFrameCols = 4;
 constexpr int kFrameMaxAlpha = 28;
 constexpr int kFrameFlagAlpha = 56;
+constexpr int kLaneFlagAlpha = (kThrF16 - 1) / (kFrameRows + kFrameCols);   // 53
 __host__ __device__ inline int frame_thr(int thr, int alpha) {
     if (alpha > kFrameFlagAlpha) return 0;
     const int c = kThrF16 - (kFrameRows + 1) * alpha;
+    return thr < c ? thr : c;
+}
+__host__ __device__ inline int lane_frame_thr(int thr, int alpha) {
+    if (alpha > kLaneFlagAlpha) return 0;
+    const int c = kThrF16 - (kFrameRows + kFrameCols) * alpha;
     return thr < c ? thr : c;
 }
 
@@ -61,7 +71,7 @@ struct InterArgs {
     int32_t *counter;        // work-queue head, zero before launch
     QuerySet qs;
     int32_t R;
-    int32_t thr;             // a lane whose best reaches thr is flagged (fp16: see frame_thr)
+    int32_t thr;             // a lane whose best reaches thr is flagged (fp16: see lane_frame_thr)
     uint32_t *scratch;       // boundary columns: per (slot, wave) max_rows * 64 * 2 dwords
     int32_t max_rows;
     int32_t *scores;         // [query][n_seqs], caller order

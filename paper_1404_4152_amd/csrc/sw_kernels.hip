@@ -13,7 +13,8 @@
 // t = h - beta between E (next row) and F (next column) gives 7.5 VALU ops per
 // cell with a 3-input max, the running best taking one max3 per two cells.
 // The fp16 tier of the lane-per-subject kernel keeps its values in a frame
-// that moves by alpha per subject row and needs 6.5 (FrameStrip below).
+// that moves by alpha per subject row and per query column within groups of
+// four columns, and needs 5.75 (FrameStrip below).
 //
 // Two kernels:
 //  * inter_kernel: one lane per subject, two subjects per 32-bit lane in packed
@@ -42,7 +43,7 @@
 // value >= thr and the running best reaches thr.
 //   F16X2: fp16 holds every integer in [-2048, 2048]; thr = 1920 keeps
 //          thr - 1 + max(M) <= 2048 for |M| <= 127 (wave-per-pair kernel; the
-//          lane-per-subject row frame lowers it by 33 alpha).  alpha and beta are
+//          lane-per-subject frame lowers it by 36 alpha).  alpha and beta are
 //          clamped to 2048: for lanes below thr a larger penalty gives the same
 //          (zero-floored) E and F.  Once flagged, values may round or reach
 //          +inf but never NaN (only finite constants are subtracted).
@@ -238,32 +239,70 @@ struct Strip {
 };
 
 // ---------------------------------------------------------------------------
-// Row-frame form of the fp16 tier (lane-per-subject kernel).
+// Frame form of the fp16 tier (lane-per-subject kernel).
 //
-// E loses alpha per subject row.  Storing every value of row r shifted by
-// c_r = r * alpha (r counted from the start of a period of kFrameRows rows)
-// cancels that decay: with H and F of row r at offset c_r, the E entering row
-// r at offset c_r, and H of row r-1 (the diagonal operand) at offset
-// c_r - alpha, made up for by a profile that holds s + alpha,
-//   h = max(hdiag + (s + alpha), e, f);   u = h + (alpha - beta);
-//   e' = max(e, u, c_r + alpha);          f' = max(f, u) - alpha
-// is Eq. 1 with e' at offset c_{r+1} = c_r + alpha and f' at offset c_r, and
-// one subtraction of a constant serves both gaps: 6.5 VALU ops per cell with
-// the running best instead of 7.5.  Only E is floored (at its offset of true
-// 0); F may go negative, which H never sees because E >= 0 (H = max(0, ...)
-// needs one floored operand).  Each period the carried H, E, floor and best
-// drop by kFrameRows * alpha; the running best is kept in the frame of the
-// current row (+alpha per row) and converted back at the end of a strip.
+// E loses alpha per subject row and F loses alpha per query column.  Cell
+// (r, j) is stored shifted by o(r, j) = c_r + alpha * (j mod G), G =
+// kFrameCols, where c_r = r * alpha (r counted from the start of a period of
+// kFrameRows rows).  Then E entering row r + 1 sits at o(r, j) + alpha and F
+// entering column j + 1 at o(r, j) + alpha unless j + 1 starts a new group of
+// G columns, where its offset drops back by (G - 1) alpha:
+//   h = max(hdiag + s', e, f);         u = h + (alpha - beta);
+//   e' = max(e, u, fl[j mod G]);       f' = max(f, u)  [- G alpha after class G-1]
+// is Eq. 1, with the diagonal's offset change folded into the profile
+// (s' = s + 2 alpha, or s + (2 - G) alpha into a class-0 column, whose
+// diagonal comes from class G - 1 of the row above).  One subtraction per G
+// columns serves F and none serves E: 5.75 VALU ops per cell with the running
+// best at G = 4, against 7.5 for the textbook form.  Only E is floored (fl[c]
+// = true 0 at offset o(r + 1, j) for class c); F may go negative, which H never
+// sees because E >= 0 (H = max(0, ...) needs one floored operand).
+//
+// Running best: cells (r, j) and (r - 1, j + 1) for even j share the offset
+// c_r + alpha * (j mod G) (j mod G < G - 1), and H(r - 1, j + 1) is the
+// diagonal operand left over after column j + 1, so one max3 per two cells
+// covers row r's even columns and row r - 1's odd ones into one register per
+// even class, each kept in the frame of the current row (+alpha per row).  The
+// last row's odd columns are taken after the last row.  Each period the carried
+// H, E, floors and bests drop by kFrameRows * alpha.
 //
 // Exactness: until the first cell whose true H reaches thr, every true value
-// lies in [-2048, thr + 126] and offsets add at most kFrameRows * alpha, so
-// thr = kThrF16 - (kFrameRows + 1) * alpha keeps all values exact integers in
-// fp16; that cell's offset H is exact and >= thr + c_r.  Rounding is monotone
-// and every offset applied is an exactly representable constant, so the
-// running best stays >= thr + its offset and the converted best >= thr: the
-// lane is flagged.  For alpha > kFrameFlagAlpha the ceiling is 0 and every
-// lane is flagged (values stay finite: offsets are at most 32 * 56).
+// lies in [-2048, thr + 126] and offsets add at most (kFrameRows + G - 1) alpha,
+// so thr = kThrF16 - (kFrameRows + G) alpha keeps all values exact integers in
+// fp16; that cell's offset H is exact and >= thr + its offset.  Rounding is
+// monotone and every offset applied is an exactly representable constant, so
+// the running best stays >= thr + its offset and the converted best >= thr:
+// the lane is flagged.  For alpha > kLaneFlagAlpha the ceiling is 0 and every
+// lane is flagged (alpha is clamped there, so values stay finite).
 // ---------------------------------------------------------------------------
+struct LaneFrame {
+    h2 nalpha;    // -alpha
+    h2 palpha;    // +alpha
+    h2 nu;        // alpha - beta
+    h2 rebase;    // -kFrameRows * alpha
+    h2 ngroup;    // -kFrameCols * alpha
+    int alpha;
+    int bias0;    // profile bias of a class-0 column: (2 - kFrameCols) * alpha
+    int bias1;    // of any other column: 2 * alpha
+    __device__ LaneFrame(int alpha_, int beta) {
+        alpha = min(alpha_, kLaneFlagAlpha);
+        beta = min(beta, 2048);
+        nalpha = k(-1);
+        palpha = k(1);
+        const _Float16 u = (_Float16)(float)(alpha - beta);
+        nu = h2{u, u};
+        rebase = k(-kFrameRows);
+        ngroup = k(-kFrameCols);
+        bias0 = (2 - kFrameCols) * alpha;
+        bias1 = 2 * alpha;
+    }
+    // n * alpha in both halves (exact: |n * alpha| <= (kFrameRows + kFrameCols) * 53)
+    __device__ h2 k(int n) const {
+        const _Float16 v = (_Float16)(float)(n * alpha);
+        return h2{v, v};
+    }
+};
+
+// Constants of the packed wave-per-pair kernel's row frame (see intra2_pass).
 struct FrameF16 {
     h2 nalpha;    // -alpha
     h2 palpha;    // +alpha
@@ -286,19 +325,22 @@ struct FrameF16 {
 
 template <int T>
 struct FrameStrip {
+    static_assert(kFrameCols == 4 && T % kFrameCols == 0, "a profile quad is one column group");
     typedef h2 V;
     static __device__ __forceinline__ V max3(V a, V b, V c) {
         return __builtin_elementwise_maximum(__builtin_elementwise_maximum(a, b), c);
     }
 
-    // One cell in the row frame; hdiag and f carry along the row.
-    static __device__ __forceinline__ V cell(const FrameF16 &ops, V &H, V &E, uint32_t s, V &hdiag,
+    // One cell of column class C; hdiag and f carry along the row.
+    template <int C>
+    static __device__ __forceinline__ V cell(const LaneFrame &ops, V &H, V &E, uint32_t s, V &hdiag,
                                              V &f, V fl) {
         const V hold = H;
         const V h = max3(hdiag + as_v<V>(s), E, f);
         const V t = h + ops.nu;
         E = max3(E, t, fl);
-        f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+        f = __builtin_elementwise_maximum(f, t);
+        if (C == kFrameCols - 1) f += ops.ngroup;
         H = h;
         hdiag = hold;
         return h;
@@ -309,48 +351,58 @@ struct FrameStrip {
     // latency hides behind the row.  Alternating the two buffers row by row
     // keeps every value in fixed registers (a single buffer refilled in place
     // makes the compiler copy it back at every loop edge).
-    // hb_prev = H(i-1, j0-1) at offset c_r - alpha, fin = F(i, j0) at offset
-    // c_r, fl = c_r + alpha; best at offset c_r.
-    static __device__ __forceinline__ void row(const FrameF16 &ops, V (&H)[T], V (&E)[T],
+    // hb_prev = H(r-1, j0-1) at offset c_r + (G-2) alpha, fin = F(r, j0) at
+    // offset c_r, FL[c] = c_r + (c+1) alpha; B[0], B[1] = running bests of
+    // classes 0 and 2, at offsets c_r and c_r + 2 alpha.
+    static __device__ __forceinline__ void row(const LaneFrame &ops, V (&H)[T], V (&E)[T],
                                                const uint4 (&Pc)[T / 4], uint4 (&Pn)[T / 4],
                                                const uint4 *nxt, uint32_t hb_prev, uint32_t fin,
-                                               V fl, V &best, uint32_t &hout, uint32_t &fout) {
+                                               const V (&FL)[kFrameCols], V (&B)[2],
+                                               uint32_t &hout, uint32_t &fout) {
         V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) Pn[j4] = nxt[j4];
 #pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) {
-            const uint32_t pv[4] = {Pc[j4].x, Pc[j4].y, Pc[j4].z, Pc[j4].w};
-#pragma unroll
-            for (int u = 0; u < 4; u += 2) {
-                const int j = j4 * 4 + u;
-                const V h0 = cell(ops, H[j], E[j], pv[u], hdiag, f, fl);
-                const V h1 = cell(ops, H[j + 1], E[j + 1], pv[u + 1], hdiag, f, fl);
-                best = max3(best, h0, h1);
-            }
+            const int j = j4 * 4;
+            const V h0 = cell<0>(ops, H[j], E[j], Pc[j4].x, hdiag, f, FL[0]);
+            cell<1>(ops, H[j + 1], E[j + 1], Pc[j4].y, hdiag, f, FL[1]);
+            B[0] = max3(B[0], h0, hdiag);          // hdiag = H(r-1, j+1)
+            const V h2v = cell<2>(ops, H[j + 2], E[j + 2], Pc[j4].z, hdiag, f, FL[2]);
+            cell<3>(ops, H[j + 3], E[j + 3], Pc[j4].w, hdiag, f, FL[3]);
+            B[1] = max3(B[1], h2v, hdiag);         // hdiag = H(r-1, j+3)
         }
         hout = as_u(H[T - 1]);
         fout = as_u(f);
 #pragma unroll
         for (int j = 0; j < T; ++j) asm volatile("" : "+v"(H[j]), "+v"(E[j]));
-        asm volatile("" : "+v"(best));
+        asm volatile("" : "+v"(B[0]), "+v"(B[1]));
     }
 
-    // All rows of one group against one strip; `best` is a true value on
+    // All rows of one group against one strip; `best_io` is a true value on
     // entry and exit.  Loads as in Strip::pass.
     template <bool HAS_IN, bool HAS_OUT>
-    static __device__ __forceinline__ void pass(const FrameF16 &ops, V &best_io,
+    static __device__ __forceinline__ void pass(const LaneFrame &ops, V &best_io,
                                                 const uint16_t *codes, uint32_t *wsc, int nch,
                                                 const uint32_t *lds, int RS) {
         constexpr int kPeriodChunks = kFrameRows / kChunk;
         V H[T], E[T];
+        // Row -1: H is the true 0 boundary at offset o(-1, j), E the true 0
+        // floor at o(0, j).
 #pragma unroll
-        for (int j = 0; j < T; ++j) { H[j] = ops.nalpha; E[j] = V{(_Float16)0.0f, (_Float16)0.0f}; }
-        V fl = ops.palpha;      // c_r + alpha
-        V z = ops.nalpha;       // true 0 at offset c_r - alpha: left edge of the first strip
-        V best = best_io;       // offset c_0 = 0
-        uint32_t hb_prev = as_u(ops.nalpha);
+        for (int j = 0; j < T; ++j) {
+            H[j] = ops.k((j & 3) - 1);
+            E[j] = ops.k(j & 3);
+        }
+        V FL[kFrameCols] = {ops.k(1), ops.k(2), ops.k(3), ops.k(4)};
+        V B[2] = {best_io, ops.k(0)};
+        // true 0 at the offset of a class-0 column's diagonal: left edge of the
+        // first strip, and the row above the first row
+        V z = ops.k(kFrameCols - 2);
+        uint32_t hb_prev = as_u(z);
+        // F left of the first strip: any true value <= 0 will do (H >= E >= 0)
+        const uint32_t f_edge = as_u(ops.nalpha);
         const int last = nch - 1;
         uint2 cd = *(const uint2 *)codes;
         uint2 cd_n = *(const uint2 *)(codes + (size_t)(last < 1 ? last : 1) * 256);
@@ -369,8 +421,10 @@ struct FrameStrip {
             if (c != 0 && c % kPeriodChunks == 0) {
 #pragma unroll
                 for (int j = 0; j < T; ++j) { H[j] += ops.rebase; E[j] += ops.rebase; }
-                fl += ops.rebase;
-                best += ops.rebase;
+#pragma unroll
+                for (int x = 0; x < kFrameCols; ++x) FL[x] += ops.rebase;
+                B[0] += ops.rebase;
+                B[1] += ops.rebase;
                 if (HAS_IN) hb_prev = as_u(as_v<V>(hb_prev) + ops.rebase);
                 else z += ops.rebase;
             }
@@ -391,11 +445,13 @@ struct FrameStrip {
             uint32_t o[8];
 #pragma unroll
             for (int x = 0; x < kChunk; ++x) {
-                const uint32_t hb = HAS_IN ? hb_in[x] : as_u(z), fi = HAS_IN ? f_in[x] : as_u(z);
-                if (x & 1) row(ops, H, E, P1, P0, nx[x], hb, fi, fl, best, o[2 * x], o[2 * x + 1]);
-                else row(ops, H, E, P0, P1, nx[x], hb, fi, fl, best, o[2 * x], o[2 * x + 1]);
-                fl += ops.palpha;
-                best += ops.palpha;
+                const uint32_t hb = HAS_IN ? hb_in[x] : as_u(z), fi = HAS_IN ? f_in[x] : f_edge;
+                if (x & 1) row(ops, H, E, P1, P0, nx[x], hb, fi, FL, B, o[2 * x], o[2 * x + 1]);
+                else row(ops, H, E, P0, P1, nx[x], hb, fi, FL, B, o[2 * x], o[2 * x + 1]);
+#pragma unroll
+                for (int y = 0; y < kFrameCols; ++y) FL[y] += ops.palpha;
+                B[0] += ops.palpha;
+                B[1] += ops.palpha;
                 if (!HAS_IN) z += ops.palpha;
             }
             hb_prev = b1.z;
@@ -409,8 +465,16 @@ struct FrameStrip {
             b0 = b0n;
             b1 = b1n;
         }
-        // best is at offset c_last + alpha = fl - alpha
-        best_io = best - (fl + ops.nalpha);
+        // The last row's odd columns (classes 1 and 3), at the offsets of B[0]
+        // and B[1] after the last row's step.
+#pragma unroll
+        for (int j = 0; j < T; j += 4) {
+            B[0] = __builtin_elementwise_maximum(B[0], H[j + 1]);
+            B[1] = __builtin_elementwise_maximum(B[1], H[j + 3]);
+        }
+        // B[0] sits at offset FL[0] - alpha, B[1] at FL[0] + alpha
+        best_io = __builtin_elementwise_maximum(B[0] - (FL[0] + ops.nalpha),
+                                                B[1] - (FL[0] + ops.palpha));
     }
 };
 
@@ -445,12 +509,13 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
         if (it >= a.n_items) break;
         const int q = a.item_q[it];
         const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
-        typedef typename std::conditional<TIER == TIER_F16X2, FrameF16, L>::type Ops;
+        typedef typename std::conditional<TIER == TIER_F16X2, LaneFrame, L>::type Ops;
         const Ops ops(min(alpha, kCap), min(beta, kCap));
-        int bias = 0, thr = a.thr;
+        int bias0 = 0, bias1 = 0, thr = a.thr;
         if constexpr (TIER == TIER_F16X2) {
-            bias = ops.bias;
-            thr = frame_thr(a.thr, alpha);
+            bias0 = ops.bias0;
+            bias1 = ops.bias1;
+            thr = lane_frame_thr(a.thr, alpha);
         }
         const int g = a.item_g[it] + w;
         const bool active = g < a.n_groups;
@@ -468,7 +533,8 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
                 const int col = k * T + 2 * jj;    // mp is even, so col < mp covers col + 1
                 const int8_t *src = qp + (size_t)r * mp + col;
                 const int s0 = col < mp ? src[0] : 0, s1 = col < mp ? src[1] : 0;
-                stage[e] = (uint32_t)L::enc(s0 + bias) | ((uint32_t)L::enc(s1 + bias) << 16);
+                const int b0 = col % kFrameCols == 0 ? bias0 : bias1;   // col + 1 is odd
+                stage[e] = (uint32_t)L::enc(s0 + b0) | ((uint32_t)L::enc(s1 + bias1) << 16);
             }
             __syncthreads();
             for (int e = threadIdx.x; e < RR * (T / 2); e += W * 64) {

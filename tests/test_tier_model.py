@@ -11,10 +11,11 @@ best reaches the threshold too).  This model replays that arithmetic, cell
 order and all, in numpy float16 / int16, vectorised over many pairs of equal
 shape, and checks the claim against the oracle, including scores far beyond
 the fp16 and int16 ranges and penalties beyond the clamps.  The lane-per-
-subject fp16 tier uses a row-frame form of the same recurrence (values of
-subject row r offset by alpha * (r mod 32), so E needs no per-row decay); its
-model replays that arithmetic with strips, frame periods and padding, against
-the ceiling 1920 - 33 alpha, with a negative control at the unshifted ceiling.
+subject fp16 tier uses a frame form of the same recurrence (cell (r, j) offset
+by alpha * ((r mod 32) + (j mod 4)), so E needs no per-row decay and F one
+decay per four columns); its model replays that arithmetic with strips, frame
+periods and padding, against the ceiling 1920 - 36 alpha, with negative
+controls at the unshifted ceiling and without the running best's last step.
 It shares no code with the kernels or the oracle; it is a model of the design,
 written from the same recurrence (section II.A, Eq. 1).
 """
@@ -81,54 +82,73 @@ def model_i16(Q, S, M, alpha, beta):
 
 
 def frame_ceiling(thr, alpha, rows=32):
-    """Ceiling of the row-frame fp16 tier for a query with gap extension alpha."""
+    """Ceiling of the packed wave-per-pair fp16 row frame for gap extension alpha."""
     if alpha > 56:
         return 0
     return min(thr, 1920 - (rows + 1) * alpha)
 
 
-def model_f16_frame(Q, S, M, alpha, beta, T=8, rows=32, chunk=4):
-    """Row-frame fp16 arithmetic of the lane-per-subject kernel, replayed in
-    numpy float16: the query in strips of T columns (boundary H and F of every
-    row handed to the next strip), subjects padded with zero-score rows to a
-    multiple of `chunk` plus one extra chunk, the query with zero-score columns
-    to a multiple of T, profile scores biased by +alpha, values of subject row
-    r offset by alpha * (r mod rows), and the carried state lowered by
-    rows * alpha at the start of every period.  Returns the converted best."""
+def lane_ceiling(thr, alpha, rows=32, G=4):
+    """Ceiling of the lane-per-subject fp16 tier (row and column-class frame)
+    for a query with gap extension alpha: offsets reach (rows + G - 1) alpha."""
+    if (rows + G) * alpha >= 1920:
+        return 0
+    return min(thr, 1920 - (rows + G) * alpha)
+
+
+def model_f16_frame(Q, S, M, alpha, beta, T=8, rows=32, chunk=4, G=4, extra_chunk=True,
+                    tail=True):
+    """Frame form of the lane-per-subject fp16 tier, replayed in numpy float16:
+    the query in strips of T columns (boundary H and F of every row handed to
+    the next strip), subjects padded with zero-score rows to a multiple of
+    `chunk` (plus one extra chunk if `extra_chunk`), the query with zero-score
+    columns to a multiple of T.  Cell (r, j) is held at offset
+    alpha * ((r mod rows) + (j mod G)): E needs no per-row decay and F needs
+    its decay only when j + 1 starts a new class group (by G alpha).  Profile
+    scores carry the diagonal's offset change (+2 alpha, or (2 - G) alpha into
+    a class-0 column), E is floored per class, and the running best pairs
+    cell (r, j) (j even) with (r - 1, j + 1), which shares its offset, into one
+    register per even class; the last row's odd columns are taken at the end
+    (`tail`).  The carried state drops by rows * alpha at every period start.
+    Returns the converted best."""
+    assert G % 2 == 0 and T % G == 0
     B, m = Q.shape
     n = S.shape[1]
     f16 = np.float16
-    a = min(alpha, 56)
+    a = alpha if (rows + G) * alpha < 1920 else 1920 // (rows + G)
     b = min(beta, 2048)
-    nalpha, palpha, nu, rb = f16(-a), f16(a), f16(a - b), f16(-rows * a)
+    nalpha, palpha, nu, rb, ng = f16(-a), f16(a), f16(a - b), f16(-rows * a), f16(-G * a)
     A = M.shape[0]
     Mx = np.zeros((A + 1, A + 1), np.int64)          # code A pads, scoring 0
     Mx[:A, :A] = M
-    n_pad = ((n + chunk - 1) // chunk) * chunk + chunk
+    n_pad = ((n + chunk - 1) // chunk) * chunk + (chunk if extra_chunk else 0)
     m_pad = ((m + T - 1) // T) * T
     Qp = np.full((B, m_pad), A, np.int64)
     Qp[:, :m] = Q
     Sp = np.full((B, n_pad), A, np.int64)
     Sp[:, :n] = S
-    prof = [(Mx[Qp, Sp[:, r:r + 1]] + a).astype(f16) for r in range(n_pad)]   # (B, m_pad) per row
+    bias = np.array([(2 - G) * a if j % G == 0 else 2 * a for j in range(m_pad)], np.int64)
+    prof = [(Mx[Qp, Sp[:, r:r + 1]] + bias).astype(f16) for r in range(n_pad)]   # (B, m_pad)
+    full = lambda v: np.full(B, f16(v), f16)
     best_true = np.zeros(B, f16)
     hb_out = f_out = None
     with np.errstate(over="ignore", invalid="ignore"):
         for k in range(m_pad // T):
             has_in = k > 0
-            H = np.full((T, B), nalpha, f16)
-            E = np.zeros((T, B), f16)
-            fl = np.full(B, palpha, f16)
-            z = np.full(B, nalpha, f16)
-            best = best_true.copy()
-            hb_prev = np.full(B, nalpha, f16)
+            H = np.stack([full(((jj % G) - 1) * a) for jj in range(T)])
+            E = np.stack([full((jj % G) * a) for jj in range(T)])    # true 0: H's floor
+            fl = [full((1 + c) * a) for c in range(G)]
+            z = full((G - 2) * a)
+            bests = {c: full(0) for c in range(0, G, 2)}
+            bests[0] = best_true.copy()
+            hb_prev = full((G - 2) * a)
             new_hb, new_f = [], []
             for r in range(n_pad):
                 if r and r % rows == 0:
                     H = (H + rb).astype(f16)
                     E = (E + rb).astype(f16)
-                    fl = (fl + rb).astype(f16)
-                    best = (best + rb).astype(f16)
+                    fl = [(x + rb).astype(f16) for x in fl]
+                    bests = {c: (x + rb).astype(f16) for c, x in bests.items()}
                     if has_in:
                         hb_prev = (hb_prev + rb).astype(f16)
                     else:
@@ -137,36 +157,51 @@ def model_f16_frame(Q, S, M, alpha, beta, T=8, rows=32, chunk=4):
                     hdiag = hb_prev if r % chunk == 0 else hb_out[r - 1]
                     f = f_out[r]
                 else:
-                    hdiag, f = z, z
+                    hdiag, f = z, full(-a)
+                h_even = None
                 for jj in range(T):
                     j = k * T + jj
+                    c = jj % G
                     hold = H[jj].copy()
                     h = np.maximum(np.maximum((hdiag + prof[r][:, j]).astype(f16), E[jj]), f)
                     t = (h + nu).astype(f16)
-                    E[jj] = np.maximum(np.maximum(E[jj], t), fl)
-                    f = (np.maximum(f, t) + nalpha).astype(f16)
+                    E[jj] = np.maximum(np.maximum(E[jj], t), fl[c])
+                    f = np.maximum(f, t)
+                    if c == G - 1:
+                        f = (f + ng).astype(f16)
                     H[jj] = h
                     hdiag = hold
-                    best = np.maximum(best, h)
+                    if jj % 2 == 0:
+                        h_even = h
+                    else:
+                        bests[c - 1] = np.maximum(np.maximum(bests[c - 1], h_even), hdiag)
                 new_hb.append(H[T - 1].copy())
                 new_f.append(f.copy())
-                fl = (fl + palpha).astype(f16)
-                best = (best + palpha).astype(f16)
+                fl = [(x + palpha).astype(f16) for x in fl]
+                bests = {c: (x + palpha).astype(f16) for c, x in bests.items()}
                 if not has_in:
                     z = (z + palpha).astype(f16)
                 if has_in and r % chunk == chunk - 1:
                     hb_prev = hb_out[r]
-            best_true = (best - (fl + nalpha).astype(f16)).astype(f16)
+            if tail:
+                for jj in range(1, T, 2):
+                    c = (jj - 1) % G
+                    bests[c] = np.maximum(bests[c], H[jj])
+            # bests[c] sits at offset fl[0] + (c - 1) alpha
+            best_true = None
+            for c, x in bests.items():
+                v = (x - (fl[0] + f16((c - 1) * a)).astype(f16)).astype(f16)
+                best_true = v if best_true is None else np.maximum(best_true, v)
             hb_out, f_out = new_hb, new_f
     assert not np.isnan(best_true).any()
     return best_true
 
 
-def check_claim(orc, Q, S, M, alpha, beta, thr, tier):
+def check_claim(orc, Q, S, M, alpha, beta, thr, tier, **kw):
     if tier == "f16":
         best = model_f16(Q, S, M, alpha, beta)
     elif tier == "frame":
-        best = model_f16_frame(Q, S, M, alpha, beta)
+        best = model_f16_frame(Q, S, M, alpha, beta, **kw)
     else:
         best = model_i16(Q, S, M, alpha, beta)
     for x in range(Q.shape[0]):
@@ -247,16 +282,31 @@ def test_model_rejects_an_invalid_fp16_threshold(orc):
 
 
 @pytest.mark.parametrize("thr", [1920, 700, 150])
-def test_f16_row_frame_random(orc, thr):
-    """Row-frame fp16 tier: subjects span several 32-row periods, the query
-    several strips; penalties across the ceiling's range (alpha 0..200)."""
+@pytest.mark.parametrize("extra_chunk", [True, False])
+def test_f16_row_frame_random(orc, thr, extra_chunk):
+    """Lane-per-subject fp16 frame: subjects span several 32-row periods, the
+    query several strips; penalties across the ceiling's range (alpha 0..200,
+    every lane flagged past 53)."""
     rng = np.random.Generator(np.random.PCG64(thr + 11))
     for A, lo, hi in [(20, -4, 11), (4, -127, 127)]:
         M = rng.integers(lo, hi + 1, size=(A, A)).astype(np.int8)
         Q = rng.integers(0, A, size=(48, 21)).astype(np.uint8)
-        S = rng.integers(0, A, size=(48, 75)).astype(np.uint8)
-        for alpha, beta in [(0, 0), (2, 12), (5, 5), (28, 40), (29, 3000), (56, 60), (57, 57), (200, 9000)]:
-            check_claim(orc, Q, S, M, alpha, beta, frame_ceiling(thr, alpha), "frame")
+        S = rng.integers(0, A, size=(48, 76)).astype(np.uint8)
+        for alpha, beta in [(0, 0), (2, 12), (5, 5), (28, 40), (29, 3000), (53, 60), (54, 54),
+                            (57, 57), (200, 9000)]:
+            check_claim(orc, Q, S, M, alpha, beta, lane_ceiling(thr, alpha), "frame",
+                        extra_chunk=extra_chunk)
+
+
+def test_f16_row_frame_two_classes(orc):
+    """The same frame with two column classes (G = 2) also holds: the model is
+    not tied to the kernel's G = 4 by accident."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    M = rng.integers(-4, 12, size=(20, 20)).astype(np.int8)
+    Q = rng.integers(0, 20, size=(48, 19)).astype(np.uint8)
+    S = rng.integers(0, 20, size=(48, 70)).astype(np.uint8)
+    for alpha, beta in [(2, 12), (5, 5), (50, 60)]:
+        check_claim(orc, Q, S, M, alpha, beta, lane_ceiling(1920, alpha, G=2), "frame", G=2)
 
 
 def test_f16_row_frame_scores_beyond_range(orc):
@@ -274,16 +324,16 @@ def test_f16_row_frame_scores_beyond_range(orc):
     S[::3, 33::5] = (S[::3, 33::5] + 1) % A
     Q[1::4, :12] = rng.integers(0, A, size=(10, 12))
     for alpha in (1, 2, 20):
-        check_claim(orc, Q, S, M, alpha, alpha + 10, frame_ceiling(1920, alpha), "frame")
+        check_claim(orc, Q, S, M, alpha, alpha + 10, lane_ceiling(1920, alpha), "frame")
     Qb = np.tile(np.arange(A, dtype=np.uint8), (3, 140))[:, :700]
-    check_claim(orc, Qb[:, :40], Qb, M, 2, 12, frame_ceiling(1920, 2), "frame")
+    check_claim(orc, Qb[:, :40], Qb, M, 2, 12, lane_ceiling(1920, 2), "frame")
 
 
 def test_frame_model_rejects_the_unshifted_ceiling(orc):
     """Negative control: with the ceiling of the unshifted form (1920) and
     alpha 20, an odd score of 1797 reached late in a 32-row period sits at an
-    offset of up to 620, past 2048 where fp16 keeps only even integers, so
-    unflagged lanes come out wrong; the frame ceiling (1260) flags them all."""
+    offset of up to 680, past 2048 where fp16 keeps only even integers, so
+    unflagged lanes come out wrong; the frame ceiling (1200) flags them all."""
     rng = np.random.Generator(np.random.PCG64(9))
     A = 5
     M = np.full((A, A), -3, np.int8)
@@ -295,9 +345,28 @@ def test_frame_model_rejects_the_unshifted_ceiling(orc):
         p = 20 + (x % 30)                   # the alignment ends at row p + 18
         S[x, p:p + 19] = Q[x]
         S[x, p + 3 + (x % 13)] = (S[x, p + 3 + (x % 13)] + 1) % A   # one mismatch: 1797
-    check_claim(orc, Q, S, M, 20, 30, frame_ceiling(1920, 20), "frame")
+    check_claim(orc, Q, S, M, 20, 30, lane_ceiling(1920, 20), "frame")
     with pytest.raises(AssertionError):
         check_claim(orc, Q, S, M, 20, 30, 1920, "frame")
+
+
+def test_frame_model_needs_the_last_row_tail(orc):
+    """The running best takes the odd columns of row r at row r + 1, so the
+    last row's odd columns need the closing step.  Queries of 16 residues
+    planted at the very end of subjects of 40 (no padding rows): the best
+    cell is the last row's last (odd) column.  Without the closing step the
+    model must come out wrong."""
+    rng = np.random.Generator(np.random.PCG64(17))
+    A = 5
+    M = np.full((A, A), -3, np.int8)
+    np.fill_diagonal(M, 60)
+    Q = rng.integers(0, A, size=(16, 16)).astype(np.uint8)
+    S = rng.integers(0, A, size=(16, 40)).astype(np.uint8)
+    S[:, 24:] = Q
+    check_claim(orc, Q, S, M, 2, 12, lane_ceiling(1920, 2), "frame", extra_chunk=False)
+    with pytest.raises(AssertionError):
+        check_claim(orc, Q, S, M, 2, 12, lane_ceiling(1920, 2), "frame", extra_chunk=False,
+                    tail=False)
 
 
 def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, init_out_shift=True):
