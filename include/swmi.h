@@ -108,6 +108,8 @@ typedef struct sw_stats {
     int32_t strip;            /* strip width used */
     int32_t waves;            /* waves per workgroup used */
     int32_t graphed;          /* 1 if the device work ran as a captured HIP graph */
+    int32_t fused_long;       /* 1 if the long list (wave-per-pair, int32) ran inside the
+                                 lane-per-subject kernel's work queue, 0 if as its own kernel */
 } sw_stats;
 
 /* Open a database (section III, stage ii: sequences are sorted by length and

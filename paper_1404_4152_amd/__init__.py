@@ -49,7 +49,8 @@ class sw_stats(ctypes.Structure):
                 ("inter_cells", ctypes.c_int64), ("recomputed_pairs", ctypes.c_int64), ("intra_pairs", ctypes.c_int64),
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("inter_ms", ctypes.c_double), ("tier", ctypes.c_int32), ("strip", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("graphed", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("graphed", ctypes.c_int32),
+                ("fused_long", ctypes.c_int32)]
 
 
 class sw_server_opts(ctypes.Structure):

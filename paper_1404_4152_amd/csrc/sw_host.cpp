@@ -159,6 +159,7 @@ struct Items {
     std::vector<int32_t> inter_q, inter_g;   // lane-per-subject: (slot, first group of block)
     std::vector<int32_t> intra_q, intra_ids; // wave-per-pair: (slot, per_item subject ids)
     int per_item = kIntraWaves;              // subjects per wave-per-pair item
+    bool fused = false;                      // wave-per-pair items run in the lane-per-subject kernel
 };
 
 // Subjects per wave of the wave-per-pair kernel: two packed fp16 halves when
@@ -170,12 +171,24 @@ int intra_per_wave(const Plan &plan, int64_t pairs, int cus) {
     return plan.tier == TIER_F16X2 && pairs >= 32LL * cus ? 2 : 1;
 }
 
+// Whether an int32 long list runs inside the lane-per-subject kernel's own
+// work queue (one subject per wave, long items first) instead of as a second
+// kernel beside it.  A second kernel's waves each take a SIMD slot that a
+// lane-per-subject wave needs (that kernel fills the register file at two
+// waves per SIMD); how much that costs depended on where the dispatcher
+// placed them, by up to 6% of a search from one process to the next.  Fused,
+// the long list only costs its own arithmetic.  Only the fp16 plan at strip
+// kFuseStrip has fused variants, and only where the wave-per-pair profile
+// fits the lane-per-subject kernel's LDS.
+bool fuse_ok(const sw_db *db, const Plan &plan, int ti);
+
 // Kernels and grids of one pass.
 struct Launch {
     Plan plan;
     int Ti = 16;
     int grid_inter = 0, grid_long = 0, grid_ovf = 0;
     bool packed_long = false;   // wave-per-pair items hold two subjects per wave
+    bool fused_long = false;    // wave-per-pair items run in the lane-per-subject kernel
 };
 
 }  // namespace
@@ -330,7 +343,7 @@ int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> 
 void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &slots,
                  const std::vector<int32_t> &mpad, const std::vector<int64_t> &qlen, int64_t b0,
                  int64_t b1, bool with_long, const std::vector<int32_t> &long_ids, int64_t stride,
-                 Items &it) {
+                 bool fuse, Items &it) {
     const int W = plan.waves;
     std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> v;
     v.reserve((size_t)slots.size() * (size_t)std::max<int64_t>(b1 - b0, 0));
@@ -352,9 +365,12 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     }
     it.intra_q.clear();
     it.intra_ids.clear();
+    it.fused = false;
     if (!with_long) return;
     const int64_t nlong = (int64_t)long_ids.size();
-    const int per = kIntraWaves * intra_per_wave(plan, nlong * (int64_t)slots.size(), db->cus);
+    const int pw = intra_per_wave(plan, nlong * (int64_t)slots.size(), db->cus);
+    it.fused = fuse && pw == 1;
+    const int per = it.fused ? W : kIntraWaves * pw;
     it.per_item = per;
     const int64_t nlblk = (nlong + per - 1) / per;
     std::vector<std::pair<int64_t, std::pair<int32_t, int64_t>>> u;
@@ -388,7 +404,7 @@ struct PassWork {
 // Items of a server pass: every (slot, block) of the work list and every
 // (slot, long-list block), each list longest first as in build_items.
 void build_work_items(const sw_db *db, const Plan &plan, const std::vector<PassWork> &work,
-                      const std::vector<int32_t> &long_ids, Items &it) {
+                      const std::vector<int32_t> &long_ids, bool fuse, Items &it) {
     const int W = plan.waves;
     std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> v;
     int64_t n_long_slots = 0;
@@ -413,7 +429,9 @@ void build_work_items(const sw_db *db, const Plan &plan, const std::vector<PassW
     it.intra_q.clear();
     it.intra_ids.clear();
     const int64_t nlong = (int64_t)long_ids.size();
-    const int per = kIntraWaves * intra_per_wave(plan, nlong * n_long_slots, db->cus);
+    const int pw = intra_per_wave(plan, nlong * n_long_slots, db->cus);
+    it.fused = fuse && pw == 1 && n_long_slots > 0 && nlong > 0;
+    const int per = it.fused ? W : kIntraWaves * pw;
     it.per_item = per;
     if (n_long_slots == 0 || nlong == 0) return;
     const int64_t nlblk = (nlong + per - 1) / per;
@@ -435,16 +453,25 @@ void build_work_items(const sw_db *db, const Plan &plan, const std::vector<PassW
 }
 
 Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_t n_inter,
-                     int64_t n_intra) {
+                     int64_t n_intra, bool fused = false) {
     Launch L;
     L.plan = plan;
     L.Ti = intra_T_for(max_qlen);
-    L.grid_inter = (int)std::min<int64_t>(n_inter, inter_max_grid(db->R, plan.tier, plan.strip, plan.waves));
+    L.fused_long = fused && n_intra > 0;
+    L.grid_inter = (int)std::min<int64_t>(
+        L.fused_long ? n_inter + n_intra : n_inter,
+        inter_max_grid(db->R, plan.tier, plan.strip, plan.waves, L.fused_long ? L.Ti : 0));
     const int per_cu = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, L.Ti) + 64), 8));
     L.grid_long = (int)std::min<int64_t>(n_intra, (int64_t)per_cu * db->cus);
     const int per_cu16 = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, 16) + 64), 8));
     L.grid_ovf = std::min(per_cu16 * db->cus * kIntraWaves, 4096);
     return L;
+}
+
+bool fuse_ok(const sw_db *db, const Plan &plan, int ti) {
+    return plan.tier == TIER_F16X2 && plan.strip == kFuseStrip &&
+           (plan.waves == 4 || plan.waves == 6 || plan.waves == 8) &&
+           intra_lds_bytes(db->R, ti) <= inter_lds_bytes(db->R, plan.strip);
 }
 
 int64_t intra_scratch_rows(const sw_db *db) {
@@ -477,7 +504,8 @@ struct PassBufs {
 int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_t st,
                  hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr, bool overlap = false) {
     HIPX(launch_fill_i32(b.counters, 0, 4, st));
-    const bool fork = overlap && b.n_inter > 0 && b.n_intra > 0;
+    const bool fused = L.fused_long && b.n_intra > 0;
+    const bool fork = overlap && !fused && b.n_inter > 0 && b.n_intra > 0;
     if (fork) {
         HIPX(hipEventRecord(db->fork, st));
         HIPX(hipStreamWaitEvent(db->aux, db->fork, 0));
@@ -509,7 +537,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
     };
     if (fork) TRY(launch_long_aux());
     if (ev_a) HIPX(hipEventRecord(ev_a, st));
-    if (b.n_inter > 0) {
+    if (b.n_inter > 0 || fused) {
         InterArgs a{};
         a.codes = db->d_codes.as<uint16_t>();
         a.grp_base = db->d_grp_base.as<int64_t>();
@@ -531,11 +559,16 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         a.ovf_id = b.ovf_id;
         a.ovf_count = b.counters + 1;
         a.ovf_cap = b.ovf_cap;
-        HIPX(launch_inter(a, L.plan.tier, L.plan.strip, L.plan.waves, L.grid_inter, st));
+        IntraArgs fl = ia;
+        fl.item_q = b.il_q;
+        fl.item_ids = b.il_ids;
+        fl.n_items = (int32_t)b.n_intra;
+        HIPX(launch_inter(a, fused ? &fl : nullptr, L.Ti, L.plan.tier, L.plan.strip, L.plan.waves,
+                          L.grid_inter, st));
     }
     if (ev_b) HIPX(hipEventRecord(ev_b, st));
     const bool packed_long = L.packed_long;
-    if (b.n_intra > 0 && !fork) {
+    if (b.n_intra > 0 && !fork && !fused) {
         IntraArgs la = ia;
         la.item_q = b.il_q;
         la.item_ids = b.il_ids;
@@ -637,11 +670,12 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     const int64_t g_cut = route_cut(db, plan, mpad, resident, long_ids);
     Items it;
     const int64_t nblk = (g_cut + plan.waves - 1) / plan.waves;
-    build_items(db, plan, slots, mpad, qlen, 0, nblk, true, long_ids, item_stride, it);
+    build_items(db, plan, slots, mpad, qlen, 0, nblk, true, long_ids, item_stride,
+                fuse_ok(db, plan, intra_T_for(max_qlen)), it);
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     if (n_inter > INT32_MAX || n_intra > INT32_MAX) return fail(SW_EINVAL, "batch too large");
-    Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra);
-    L.packed_long = it.per_item == 2 * kIntraWaves;
+    Launch L = launch_config(db, plan, max_qlen, n_inter, n_intra, it.fused);
+    L.packed_long = !it.fused && it.per_item == 2 * kIntraWaves;
     const int32_t rows_alloc = g_cut > 0 ? db->grp_rows[g_cut - 1] : 0;
     int64_t long_res = 0;
     for (int32_t id : long_ids) long_res += db->len[id];
@@ -654,7 +688,10 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     TRY(db->w_ovf.reserve((size_t)nq * n * 8 + 8));
     if (n_inter > 0)
         TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * rows_alloc * 512));
-    const int64_t intra_slots = std::max<int64_t>((int64_t)L.grid_long * kIntraWaves, L.grid_ovf);
+    // wave-per-pair scratch: one slot per wave of whichever kernel runs the long list
+    const int64_t long_slots = L.fused_long ? (int64_t)L.grid_inter * plan.waves
+                                            : (int64_t)L.grid_long * kIntraWaves;
+    const int64_t intra_slots = std::max<int64_t>(long_slots, L.grid_ovf);
     TRY(db->w_scr_intra.reserve((size_t)intra_slots * intra_scratch_rows(db) * 8));
     if (k > 0) {
         TRY(db->w_topk.reserve(topk_work_bytes(nq, k)));
@@ -799,6 +836,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     s.strip = plan.strip;
     s.waves = plan.waves;
     s.graphed = graphed ? 1 : 0;
+    s.fused_long = L.fused_long ? 1 : 0;
     return SW_OK;
 }
 
@@ -995,6 +1033,8 @@ struct sw_server {
         d_rows;
     HostBuf h_items, h_meta, h_top, h_rows;
     Launch L;
+    bool fuse = false;           // int32 long-list items may run in the lane-per-subject kernel
+    int grid_fused = 0;          // resident workgroups of that fused kernel
     // host state
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -1070,6 +1110,8 @@ int server_setup(sw_server *s) {
     const int64_t intra_items = (int64_t)s->slots * nlblk;
     s->L = launch_config(db, s->plan, 1 << 14, std::max<int64_t>(inter_items, 1),
                          std::max<int64_t>(intra_items, 1));
+    s->fuse = fuse_ok(db, s->plan, s->L.Ti);
+    s->grid_fused = s->fuse ? inter_max_grid(db->R, s->plan.tier, s->plan.strip, W, s->L.Ti) : 0;
     TRY(s->d_meta.reserve((size_t)s->slots * 24 + 256));
     TRY(s->h_meta.reserve((size_t)s->slots * 24 + 256));
     std::memset(s->h_meta.p, 0, (size_t)s->slots * 24 + 256);
@@ -1080,8 +1122,11 @@ int server_setup(sw_server *s) {
     TRY(s->d_counters.reserve(256));
     s->scr_rows = s->g_cut > 0 ? db->grp_rows[s->g_cut - 1] : 0;
     if (s->g_cut > 0)
-        TRY(s->d_scr_inter.reserve((size_t)s->L.grid_inter * W * s->scr_rows * 512));
-    const int64_t islots = std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, s->L.grid_ovf);
+        TRY(s->d_scr_inter.reserve((size_t)std::max(s->L.grid_inter, s->grid_fused) * W *
+                                   s->scr_rows * 512));
+    const int64_t islots = std::max<int64_t>(
+        std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, (int64_t)s->grid_fused * W),
+        s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
     // a pass may hold lane-per-subject and wave-per-pair items together
     const size_t items_bytes = (size_t)(inter_items * 2 + intra_items * (1 + per) + 64) * 4;
@@ -1186,7 +1231,7 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     std::sort(riders.begin(), riders.end());
     riders.erase(std::unique(riders.begin(), riders.end()), riders.end());
     Items it;
-    build_work_items(db, s->plan, work, s->long_ids, it);
+    build_work_items(db, s->plan, work, s->long_ids, s->fuse, it);
     const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
     int32_t *hi = s->h_items.as<int32_t>();
     std::memcpy(hi, it.inter_q.data(), n_inter * 4);
@@ -1217,8 +1262,11 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.scr_rows = s->scr_rows;
     pb.scr_intra = s->d_scr_intra.as<int32_t>();
     Launch L = s->L;
-    L.packed_long = it.per_item == 2 * kIntraWaves;
-    L.grid_inter = (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
+    L.fused_long = it.fused && n_intra > 0;
+    L.packed_long = !it.fused && it.per_item == 2 * kIntraWaves;
+    L.grid_inter = L.fused_long
+                       ? (int)std::min<int64_t>(n_inter + n_intra, s->grid_fused)
+                       : (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
     L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
     TRY(enqueue_pass(db, L, pb, st, nullptr, nullptr, true));
     // requests that visited their last position get top-k

@@ -105,10 +105,16 @@ struct IntraArgs {
 hipError_t prepare_kernels();
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
-                        hipStream_t st);
-int inter_lds_bytes(int R, int strip);
-int inter_max_grid(int R, int tier, int strip, int waves);   // resident workgroups that fit
+// The lane-per-subject kernel; with `la` non-null and ti in {4, 8, 16} (fp16
+// tier at strip kFuseStrip only) it first works through la's wave-per-pair
+// items, one subject per wave (la.item_ids holds `waves` ids per item), with
+// the wave-per-pair strip ti, in its own workgroups.
+constexpr int kFuseStrip = 32;
+hipError_t launch_inter(const InterArgs &a, const IntraArgs *la, int ti, int tier, int strip,
+                        int waves, int grid, hipStream_t st);
+int inter_lds_bytes(int R, int strip, int ti = 0);
+// resident workgroups that fit (ti as for launch_inter)
+int inter_max_grid(int R, int tier, int strip, int waves, int ti = 0);
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);

@@ -484,8 +484,16 @@ template <int T, int TIER> struct InterOcc {
     static constexpr int value = T <= 16 ? (TIER == TIER_F16X2 ? 3 : 4) : (T <= 32 ? 2 : 1);
 };
 
-template <int T, int W, int TIER>
-__global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kernel(InterArgs a, int magic) {
+template <int T, int W>
+__device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t *lds,
+                                           int32_t *wsc);
+
+// TI > 0: the work queue first hands out the long list's wave-per-pair items
+// (`la`, one subject per wave, strip TI), then the lane-per-subject items, so
+// the long list runs in this kernel's own workgroup slots.
+template <int T, int W, int TIER, int TI>
+__global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value))
+    inter_kernel(InterArgs a, IntraArgs la, int magic) {
     typedef Lane<TIER> L;
     typedef typename L::V V;
     constexpr int RS = T + 4;                 // dwords per pair-profile row (padded)
@@ -501,11 +509,21 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
     // to 0 anyway, so they are clamped to it.
     constexpr int kCap = TIER == TIER_I16X2 ? 32767 : 2048;
     uint32_t *wsc = a.scratch + ((size_t)(blockIdx.x * W + w) * (size_t)a.max_rows) * 128 + lane * 8;
+    const int n_long = TI > 0 ? la.n_items : 0;
 
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
-        const int it = s_item;
+        int it = s_item;
+        if constexpr (TI > 0) {
+            if (it < n_long) {
+                const int wv = __builtin_amdgcn_readfirstlane(w);
+                int32_t *lwsc = la.pass_scratch + (size_t)(blockIdx.x * W + wv) * (size_t)la.max_len_pad * 2;
+                intra_item<TI, W>(la, it, lds, lwsc);   // its first barrier orders the read of s_item
+                continue;
+            }
+            it -= n_long;
+        }
         if (it >= a.n_items) break;
         const int q = a.item_q[it];
         const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
@@ -580,22 +598,34 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value)) inter_kern
     }
 }
 
-int inter_lds_bytes(int R, int strip) {
-    return (R * R * (strip + 4) + R * (strip / 2)) * 4;
+int inter_lds_bytes(int R, int strip, int ti) {
+    const int lane = (R * R * (strip + 4) + R * (strip / 2)) * 4;
+    return ti > 0 ? std::max(lane, intra_lds_bytes(R, ti)) : lane;
 }
 
 static int lds_per_cu() { return 160 * 1024; }
 
-template <int T, int W, int TIER>
+template <int T, int W, int TIER, int TI>
 static int inter_resident_t(int R) {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inter_kernel<T, W, TIER>, W * 64,
-                                                     inter_lds_bytes(R, T)) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inter_kernel<T, W, TIER, TI>, W * 64,
+                                                     inter_lds_bytes(R, T, TI)) != hipSuccess)
         per_cu = 0;
     return per_cu;
 }
 
-int inter_max_grid(int R, int tier, int strip, int waves) {
+template <int T, int W, int TIER>
+static int inter_resident_ti(int R, int ti) {
+    if (ti == 0) return inter_resident_t<T, W, TIER, 0>(R);
+    if constexpr (T == kFuseStrip && TIER == TIER_F16X2) {
+        if (ti == 4) return inter_resident_t<T, W, TIER, 4>(R);
+        if (ti == 8) return inter_resident_t<T, W, TIER, 8>(R);
+        if (ti == 16) return inter_resident_t<T, W, TIER, 16>(R);
+    }
+    return 0;
+}
+
+int inter_max_grid(int R, int tier, int strip, int waves, int ti) {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
         hipDeviceProp_t p;
@@ -605,15 +635,15 @@ int inter_max_grid(int R, int tier, int strip, int waves) {
     int per_cu = 0;
 #define SWMI_RES_CASE(T_, W_)                                                              \
     if (strip == T_ && waves == W_)                                                        \
-        per_cu = tier == TIER_I16X2 ? inter_resident_t<T_, W_, TIER_I16X2>(R)             \
-                                    : inter_resident_t<T_, W_, TIER_F16X2>(R);
+        per_cu = tier == TIER_I16X2 ? inter_resident_ti<T_, W_, TIER_I16X2>(R, ti)        \
+                                    : inter_resident_ti<T_, W_, TIER_F16X2>(R, ti);
     SWMI_RES_CASE(16, 4) SWMI_RES_CASE(16, 8)
     SWMI_RES_CASE(32, 4) SWMI_RES_CASE(32, 6) SWMI_RES_CASE(32, 8)
     SWMI_RES_CASE(64, 4)
 #undef SWMI_RES_CASE
     if (per_cu < 1) {
         // runtime query unavailable: bound by LDS and 8 waves per SIMD
-        const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip) + 64);
+        const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip, ti) + 64);
         const int by_waves = 32 / waves;
         per_cu = by_lds < by_waves ? by_lds : by_waves;
         if (per_cu < 1) per_cu = 1;
@@ -621,19 +651,32 @@ int inter_max_grid(int R, int tier, int strip, int waves) {
     return per_cu * cus;
 }
 
-template <int T, int W, int TIER>
-static hipError_t launch_inter_t(const InterArgs &a, int grid, hipStream_t st) {
+template <int T, int W, int TIER, int TI>
+static hipError_t launch_inter_t(const InterArgs &a, const IntraArgs &la, int grid, hipStream_t st) {
     int magic = (65536 + a.R - 1) / a.R;
-    const int lds = inter_lds_bytes(a.R, T);
-    hipLaunchKernelGGL((inter_kernel<T, W, TIER>), dim3(grid), dim3(W * 64), lds, st, a, magic);
+    const int lds = inter_lds_bytes(a.R, T, TI);
+    hipLaunchKernelGGL((inter_kernel<T, W, TIER, TI>), dim3(grid), dim3(W * 64), lds, st, a, la,
+                       magic);
     return hipGetLastError();
 }
 
+template <int T, int W, int TIER>
+static hipError_t launch_inter_ti(const InterArgs &a, const IntraArgs *la, int ti, int grid,
+                                  hipStream_t st) {
+    if (!la || ti == 0) return launch_inter_t<T, W, TIER, 0>(a, IntraArgs{}, grid, st);
+    if constexpr (T == kFuseStrip && TIER == TIER_F16X2) {
+        if (ti == 4) return launch_inter_t<T, W, TIER, 4>(a, *la, grid, st);
+        if (ti == 8) return launch_inter_t<T, W, TIER, 8>(a, *la, grid, st);
+        if (ti == 16) return launch_inter_t<T, W, TIER, 16>(a, *la, grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 template <int TIER>
-static hipError_t launch_inter_tier(const InterArgs &a, int strip, int waves, int grid,
-                                    hipStream_t st) {
+static hipError_t launch_inter_tier(const InterArgs &a, const IntraArgs *la, int ti, int strip,
+                                    int waves, int grid, hipStream_t st) {
 #define SWMI_INTER_CASE(T_, W_) \
-    if (strip == T_ && waves == W_) return launch_inter_t<T_, W_, TIER>(a, grid, st);
+    if (strip == T_ && waves == W_) return launch_inter_ti<T_, W_, TIER>(a, la, ti, grid, st);
     SWMI_INTER_CASE(16, 4) SWMI_INTER_CASE(16, 8)
     SWMI_INTER_CASE(32, 4) SWMI_INTER_CASE(32, 6) SWMI_INTER_CASE(32, 8)
     SWMI_INTER_CASE(64, 4)
@@ -641,10 +684,10 @@ static hipError_t launch_inter_tier(const InterArgs &a, int strip, int waves, in
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_inter(const InterArgs &a, int tier, int strip, int waves, int grid,
-                        hipStream_t st) {
-    if (tier == TIER_F16X2) return launch_inter_tier<TIER_F16X2>(a, strip, waves, grid, st);
-    if (tier == TIER_I16X2) return launch_inter_tier<TIER_I16X2>(a, strip, waves, grid, st);
+hipError_t launch_inter(const InterArgs &a, const IntraArgs *la, int ti, int tier, int strip,
+                        int waves, int grid, hipStream_t st) {
+    if (tier == TIER_F16X2) return launch_inter_tier<TIER_F16X2>(a, la, ti, strip, waves, grid, st);
+    if (tier == TIER_I16X2) return launch_inter_tier<TIER_I16X2>(a, la, ti, strip, waves, grid, st);
     return hipErrorInvalidValue;
 }
 
@@ -701,99 +744,107 @@ __device__ __forceinline__ void intra_row(int (&H)[T], int (&E)[T], const uint2 
     fout = f;
 }
 
+// One wave-per-pair item: the W waves of the workgroup share the query's
+// profile (built per pass in `lds`) and each aligns one subject of the item.
+// Every wave reaches every barrier (waves without a subject skip the rows).
 template <int T, int W>
-__global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
+__device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t *lds,
+                                           int32_t *wsc) {
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // int16 per profile row (padded)
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     int16_t *prof = (int16_t *)lds;
-    __shared__ int s_item;
-
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
     const int pad = a.R - 1;
+    const int q = a.item_q[it];
+    const int id = a.item_ids[(size_t)it * W + w];
+    const int64_t n64 = id >= 0 ? a.off[id + 1] - a.off[id] : 0;
+    const int n = (int)n64;
+    const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
+    const int mp = a.qs.mpad[q];
+    const int npass = (a.qs.qlen[q] + PW - 1) / PW;
+    const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
+    const int8_t *qp = a.qs.qp[q];
+    int best = 0;
+
+    for (int p = 0; p < npass; ++p) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
+            const int r = e / PW, c = e - r * PW;
+            const int col = p * PW + c;
+            prof[r * RS + c] = col < mp ? (int16_t)qp[(size_t)r * mp + col] : (int16_t)0;
+        }
+        __syncthreads();
+        if (n <= 0) continue;
+
+        const bool has_in = p > 0, has_out = p + 1 < npass;
+        const int nblk = (n + 63) / 64;
+        const int steps = has_out ? nblk * 64 + 63 : n + 63;
+        int H[T], E[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
+        int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
+        // Feeders: lane k holds the data of subject row 64*b + k; lane 0's
+        // value is consumed each step, then the feeder shifts down a lane.
+        int fR, fH, fF, nR, nH, nF;
+        {
+            const int row = lane;
+            fR = row < n ? s[row] : pad;
+            fH = (has_in && row < n) ? wsc[2 * row] : 0;
+            fF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+            const int row2 = 64 + lane;
+            nR = row2 < n ? s[row2] : pad;
+            nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
+            nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
+        }
+        for (int t = 0; t < steps; ++t) {
+            if (t > 0 && (t & 63) == 0) {
+                fR = nR; fH = nH; fF = nF;
+                const int row = t + 64 + lane;
+                nR = row < n ? s[row] : pad;
+                nH = (has_in && row < n) ? wsc[2 * row] : 0;
+                nF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+            }
+            r = shr1(fR, r);
+            const int hin = shr1(fH, hout);
+            const int fin = shr1(fF, fout);
+            fR = shl1(fR, fR);
+            fH = shl1(fH, fH);
+            fF = shl1(fF, fF);
+            const uint2 *pr = (const uint2 *)(prof + r * RS + lane * T);
+            intra_row<T>(H, E, pr, hb_prev, fin, alpha, beta, best, hout, fout);
+            hb_prev = hin;
+            if (has_out) {
+                cH = shl1(hout, cH);
+                cF = shl1(fout, cF);
+                if ((t & 63) == 62 && t >= 126) {
+                    const int row = t - 126 + lane;
+                    wsc[2 * row] = cH;
+                    wsc[2 * row + 1] = cF;
+                }
+            }
+        }
+    }
+    if (id >= 0) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+        if (lane == 0) a.scores[(size_t)q * a.n_seqs + id] = best;
+    }
+}
+
+template <int T, int W>
+__global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    __shared__ int s_item;
+    const int w = threadIdx.x >> 6;
     int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
     const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
-
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
         __syncthreads();
         const int it = s_item;
         if (it >= n_items) break;
-        const int q = a.item_q[it];
-        const int id = a.item_ids[(size_t)it * W + w];
-        const int64_t n64 = id >= 0 ? a.off[id + 1] - a.off[id] : 0;
-        const int n = (int)n64;
-        const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
-        const int mp = a.qs.mpad[q];
-        const int npass = (a.qs.qlen[q] + PW - 1) / PW;
-        const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
-        const int8_t *qp = a.qs.qp[q];
-        int best = 0;
-
-        for (int p = 0; p < npass; ++p) {
-            __syncthreads();
-            for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
-                const int r = e / PW, c = e - r * PW;
-                const int col = p * PW + c;
-                prof[r * RS + c] = col < mp ? (int16_t)qp[(size_t)r * mp + col] : (int16_t)0;
-            }
-            __syncthreads();
-            if (n <= 0) continue;
-
-            const bool has_in = p > 0, has_out = p + 1 < npass;
-            const int nblk = (n + 63) / 64;
-            const int steps = has_out ? nblk * 64 + 63 : n + 63;
-            int H[T], E[T];
-#pragma unroll
-            for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
-            int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
-            // Feeders: lane k holds the data of subject row 64*b + k; lane 0's
-            // value is consumed each step, then the feeder shifts down a lane.
-            int fR, fH, fF, nR, nH, nF;
-            {
-                const int row = lane;
-                fR = row < n ? s[row] : pad;
-                fH = (has_in && row < n) ? wsc[2 * row] : 0;
-                fF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
-                const int row2 = 64 + lane;
-                nR = row2 < n ? s[row2] : pad;
-                nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
-                nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
-            }
-            for (int t = 0; t < steps; ++t) {
-                if (t > 0 && (t & 63) == 0) {
-                    fR = nR; fH = nH; fF = nF;
-                    const int row = t + 64 + lane;
-                    nR = row < n ? s[row] : pad;
-                    nH = (has_in && row < n) ? wsc[2 * row] : 0;
-                    nF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
-                }
-                r = shr1(fR, r);
-                const int hin = shr1(fH, hout);
-                const int fin = shr1(fF, fout);
-                fR = shl1(fR, fR);
-                fH = shl1(fH, fH);
-                fF = shl1(fF, fF);
-                const uint2 *pr = (const uint2 *)(prof + r * RS + lane * T);
-                intra_row<T>(H, E, pr, hb_prev, fin, alpha, beta, best, hout, fout);
-                hb_prev = hin;
-                if (has_out) {
-                    cH = shl1(hout, cH);
-                    cF = shl1(fout, cF);
-                    if ((t & 63) == 62 && t >= 126) {
-                        const int row = t - 126 + lane;
-                        wsc[2 * row] = cH;
-                        wsc[2 * row + 1] = cF;
-                    }
-                }
-            }
-        }
-        if (id >= 0) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
-            if (lane == 0) a.scores[(size_t)q * a.n_seqs + id] = best;
-        }
+        intra_item<T, W>(a, it, lds, wsc);   // its first barrier orders the read of s_item
     }
 }
 
@@ -1258,19 +1309,23 @@ hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, const int32
 }
 
 hipError_t prepare_kernels() {
+#define SWMI_K(T_, W_, TIER_, TI_) (const void *)inter_kernel<T_, W_, TIER_, TI_>
+#define SWMI_FUSED(W_, TIER_) \
+    SWMI_K(kFuseStrip, W_, TIER_, 4), SWMI_K(kFuseStrip, W_, TIER_, 8), SWMI_K(kFuseStrip, W_, TIER_, 16)
     const void *ks[] = {
-        (const void *)inter_kernel<16, 4, TIER_F16X2>, (const void *)inter_kernel<16, 8, TIER_F16X2>,
-        (const void *)inter_kernel<32, 4, TIER_F16X2>, (const void *)inter_kernel<32, 6, TIER_F16X2>,
-        (const void *)inter_kernel<32, 8, TIER_F16X2>, (const void *)inter_kernel<64, 4, TIER_F16X2>,
-        (const void *)inter_kernel<16, 4, TIER_I16X2>, (const void *)inter_kernel<16, 8, TIER_I16X2>,
-        (const void *)inter_kernel<32, 4, TIER_I16X2>, (const void *)inter_kernel<32, 6, TIER_I16X2>,
-        (const void *)inter_kernel<32, 8, TIER_I16X2>, (const void *)inter_kernel<64, 4, TIER_I16X2>,
+        SWMI_K(16, 4, TIER_F16X2, 0), SWMI_K(16, 8, TIER_F16X2, 0), SWMI_K(32, 4, TIER_F16X2, 0),
+        SWMI_K(32, 6, TIER_F16X2, 0), SWMI_K(32, 8, TIER_F16X2, 0), SWMI_K(64, 4, TIER_F16X2, 0),
+        SWMI_K(16, 4, TIER_I16X2, 0), SWMI_K(16, 8, TIER_I16X2, 0), SWMI_K(32, 4, TIER_I16X2, 0),
+        SWMI_K(32, 6, TIER_I16X2, 0), SWMI_K(32, 8, TIER_I16X2, 0), SWMI_K(64, 4, TIER_I16X2, 0),
+        SWMI_FUSED(4, TIER_F16X2), SWMI_FUSED(6, TIER_F16X2), SWMI_FUSED(8, TIER_F16X2),
         (const void *)intra_kernel<4, 1>,  (const void *)intra_kernel<8, 1>,
         (const void *)intra_kernel<16, 1>, (const void *)intra_kernel<4, 4>,
         (const void *)intra_kernel<8, 4>,  (const void *)intra_kernel<16, 4>,
         (const void *)intra2_kernel<4, 4>, (const void *)intra2_kernel<8, 4>,
         (const void *)intra2_kernel<16, 4>,
     };
+#undef SWMI_FUSED
+#undef SWMI_K
     for (const void *k : ks) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            160 * 1024 - 64);

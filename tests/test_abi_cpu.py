@@ -70,3 +70,37 @@ def test_null_handle_calls(swmi):
     swmi.lib().sw_server_stop(None)       # ignored
     rc = swmi.lib().sw_db_set_opts(None, None)
     assert rc == swmi.SW_EINVAL
+
+
+STRUCTS = ["sw_scoring", "sw_db_opts", "sw_search_opts", "sw_stats", "sw_server_opts", "sw_req_stats"]
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct the binding passes across the boundary has the header's
+    size and field offsets (a C program built against include/swmi.h prints
+    them; the binding's ctypes layout must agree field by field)."""
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_1404_4152_amd as p
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "swmi.h"', "int main(void) {"]
+    for name in STRUCTS:
+        lines.append(f'    printf("{name} %zu\\n", sizeof({name}));')
+        for f, _ in getattr(p, name)._fields_:
+            lines.append(f'    printf("{name}.{f} %zu\\n", offsetof({name}, {f}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                  text=True).stdout.split("\n") if l)
+    for name in STRUCTS:
+        cls = getattr(p, name)
+        assert int(out[name]) == ctypes.sizeof(cls), name
+        for f, _ in cls._fields_:
+            assert int(out[f"{name}.{f}"]) == getattr(cls, f).offset, f"{name}.{f}"

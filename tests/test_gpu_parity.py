@@ -67,6 +67,43 @@ def test_random_db_all_routes(swmi, orc, route, tier):
         db.close()
 
 
+@pytest.mark.parametrize("waves", [4, 6, 8])
+def test_long_list_in_lane_kernel(swmi, orc, waves):
+    """fp16 plan at strip 32: the int32 long list runs inside the lane-per-
+    subject kernel's work queue (long items first, one subject per wave).
+    Subjects up to 700 residues, those above 350 on the long list; queries
+    reach all three wave-per-pair strips (4, 8 and 16 columns per lane) and
+    several passes.  The same database at strip 16 runs the long list as its
+    own kernel beside the lane-per-subject one; both must equal the oracle, and
+    so must a graph-captured batch of the fused form."""
+    rng = np.random.Generator(np.random.PCG64(900 + waves))
+    A = 20
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 128 * waves * 2 + 300, A, 0, 700, zero_every=41)
+    db = swmi.Database(res, off, A, long_threshold=350)
+    try:
+        for strip, fused in [(32, 1), (16, 0)]:
+            db.set_opts(tier=1, strip=strip, waves=waves if strip == 32 else 4)
+            for L in [3, 256, 257, 512, 513, 1500]:
+                q = sd.random_residues(rng, L)
+                print(f"waves={waves} strip={strip} qlen={L}", flush=True)
+                expect_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12),
+                             f"waves {waves} strip {strip} qlen {L}")
+                st = db.stats()
+                assert st["fused_long"] == fused and st["intra_pairs"] > 0 and st["inter_cells"] > 0
+        db.set_opts(tier=1, strip=32, waves=waves)
+        qs = [sd.random_residues(rng, L) for L in (40, 300, 700)]
+        print(f"waves={waves} batch", flush=True)
+        for rep in range(2):   # capture, then replay
+            ts, ti, al = db.search_batch(qs, M, 2, 12, 5, all_scores=True)
+            assert db.stats()["fused_long"] == 1
+            al = np.asarray(al).reshape(len(qs), -1)
+            for x, q in enumerate(qs):
+                expect_equal(al[x], orc.search(q, res, off, M, 2, 12), f"batch rep {rep} q{x}")
+    finally:
+        db.close()
+
+
 @pytest.mark.parametrize("tier,strip,waves", [(1, 16, 4), (1, 16, 8), (1, 32, 4), (1, 32, 6),
                                               (1, 32, 8), (1, 64, 4), (2, 16, 4), (2, 32, 8),
                                               (2, 64, 4)])
