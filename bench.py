@@ -116,8 +116,9 @@ def run_plain(args, swmi, sd, torch):
         with tempfile.TemporaryDirectory() as td:
             cache = os.path.join(td, "plans.json")
             swmi.sw_db_autotune(db.h, M, w.alpha, w.beta, [len(q) for q in queries], cache)
+            # no table when nothing runs lane-per-subject (e.g. long_tail)
             tuned = [[e["bucket"], e["tier"], e["strip"], e["waves"], e["gcups"]]
-                     for e in json.load(open(cache))["entries"]]
+                     for e in json.load(open(cache))["entries"]] if os.path.exists(cache) else []
         log(f"[bench] autotuned plans in {time.perf_counter() - t0:.1f}s: {tuned}")
     # kernels, HIP events and torch's synchronisation share torch's current stream
     sptr = torch.cuda.current_stream().cuda_stream
