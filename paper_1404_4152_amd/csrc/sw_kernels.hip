@@ -352,13 +352,13 @@ struct FrameStrip {
     // keeps every value in fixed registers (a single buffer refilled in place
     // makes the compiler copy it back at every loop edge).
     // hb_prev = H(r-1, j0-1) at offset c_r + (G-2) alpha, fin = F(r, j0) at
-    // offset c_r, FL[c] = c_r + (c+1) alpha; B[0], B[1] = running bests of
-    // classes 0 and 2, at offsets c_r and c_r + 2 alpha.
+    // offset c_r, FL[c] = c_r + (c+1) alpha (the E floor of class c); B[0],
+    // B[1] = running bests of classes 0 and 2, at offsets c_r and c_r + 2 alpha.
     static __device__ __forceinline__ void row(const LaneFrame &ops, V (&H)[T], V (&E)[T],
                                                const uint4 (&Pc)[T / 4], uint4 (&Pn)[T / 4],
                                                const uint4 *nxt, uint32_t hb_prev, uint32_t fin,
-                                               const V (&FL)[kFrameCols], V (&B)[2],
-                                               uint32_t &hout, uint32_t &fout) {
+                                               const V *FL, V (&B)[2], uint32_t &hout,
+                                               uint32_t &fout) {
         V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
@@ -395,7 +395,14 @@ struct FrameStrip {
             H[j] = ops.k((j & 3) - 1);
             E[j] = ops.k(j & 3);
         }
-        V FL[kFrameCols] = {ops.k(1), ops.k(2), ops.k(3), ops.k(4)};
+        // E floors: class c of chunk row x uses FL[x + c] = c_r + (x + c + 1) alpha
+        // (row r + 1's class c floor is row r's class c + 1 floor), so the
+        // seven floors of a chunk move once per chunk.
+        constexpr int kFloors = kChunk + kFrameCols - 1;
+        V FL[kFloors];
+#pragma unroll
+        for (int x = 0; x < kFloors; ++x) FL[x] = ops.k(x + 1);
+        const V chunk_step = ops.k(kChunk);
         V B[2] = {best_io, ops.k(0)};
         // true 0 at the offset of a class-0 column's diagonal: left edge of the
         // first strip, and the row above the first row
@@ -422,7 +429,7 @@ struct FrameStrip {
 #pragma unroll
                 for (int j = 0; j < T; ++j) { H[j] += ops.rebase; E[j] += ops.rebase; }
 #pragma unroll
-                for (int x = 0; x < kFrameCols; ++x) FL[x] += ops.rebase;
+                for (int x = 0; x < kFloors; ++x) FL[x] += ops.rebase;
                 B[0] += ops.rebase;
                 B[1] += ops.rebase;
                 if (HAS_IN) hb_prev = as_u(as_v<V>(hb_prev) + ops.rebase);
@@ -446,14 +453,14 @@ struct FrameStrip {
 #pragma unroll
             for (int x = 0; x < kChunk; ++x) {
                 const uint32_t hb = HAS_IN ? hb_in[x] : as_u(z), fi = HAS_IN ? f_in[x] : f_edge;
-                if (x & 1) row(ops, H, E, P1, P0, nx[x], hb, fi, FL, B, o[2 * x], o[2 * x + 1]);
-                else row(ops, H, E, P0, P1, nx[x], hb, fi, FL, B, o[2 * x], o[2 * x + 1]);
-#pragma unroll
-                for (int y = 0; y < kFrameCols; ++y) FL[y] += ops.palpha;
+                if (x & 1) row(ops, H, E, P1, P0, nx[x], hb, fi, FL + x, B, o[2 * x], o[2 * x + 1]);
+                else row(ops, H, E, P0, P1, nx[x], hb, fi, FL + x, B, o[2 * x], o[2 * x + 1]);
                 B[0] += ops.palpha;
                 B[1] += ops.palpha;
                 if (!HAS_IN) z += ops.palpha;
             }
+#pragma unroll
+            for (int x = 0; x < kFloors; ++x) FL[x] += chunk_step;
             hb_prev = b1.z;
             if (HAS_OUT) {
                 uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
