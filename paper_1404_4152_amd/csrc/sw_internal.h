@@ -23,24 +23,17 @@ constexpr int kQPad = 32;
 // Exactness ceilings of the narrow tiers (see sw_kernels.hip for the proofs).
 constexpr int kThrF16 = 1920;    // fp16 holds every integer in [-2048, 2048]
 constexpr int kThrI16 = 32767;   // saturating int16
-// The fp16 kernels keep values in frames that move by alpha per row (see
-// sw_kernels.hip).  The packed wave-per-pair kernel offsets by up to
-// kFrameRows * alpha: ceiling kThrF16 - (kFrameRows + 1) * alpha, every lane
-// flagged above kFrameFlagAlpha.  The lane-per-subject kernel also offsets
-// the columns of each group of kFrameCols by alpha per column, up to
-// (kFrameRows + kFrameCols - 1) * alpha: ceiling
-// kThrF16 - (kFrameRows + kFrameCols) * alpha, every lane flagged above
-// kLaneFlagAlpha.  Above kFrameMaxAlpha the planner prefers the int16 tier.
+// The fp16 kernels keep values in a frame that moves by alpha per subject
+// row and per column within groups of kFrameCols (see sw_kernels.hip).
+// Offsets reach (kFrameRows + kFrameCols - 1) * alpha, so the ceiling for a
+// query with gap extension alpha is kThrF16 - (kFrameRows + kFrameCols) *
+// alpha; the lane-per-subject kernel flags every lane above kLaneFlagAlpha.
+// Above kFrameMaxAlpha the planner prefers the int16 tier, and the packed
+// wave-per-pair kernel flags every pair.
 constexpr int kFrameRows = 32;
 constexpr int kFrameCols = 4;
 constexpr int kFrameMaxAlpha = 28;
-constexpr int kFrameFlagAlpha = 56;
 constexpr int kLaneFlagAlpha = (kThrF16 - 1) / (kFrameRows + kFrameCols);   // 53
-__host__ __device__ inline int frame_thr(int thr, int alpha) {
-    if (alpha > kFrameFlagAlpha) return 0;
-    const int c = kThrF16 - (kFrameRows + 1) * alpha;
-    return thr < c ? thr : c;
-}
 __host__ __device__ inline int lane_frame_thr(int thr, int alpha) {
     if (alpha > kLaneFlagAlpha) return 0;
     const int c = kThrF16 - (kFrameRows + kFrameCols) * alpha;

@@ -68,7 +68,7 @@ __device__ __forceinline__ uint32_t as_u(V v) { return __builtin_bit_cast(uint32
 // ---------------------------------------------------------------------------
 template <int TIER> struct Lane;
 
-// The fp16 tier's cell arithmetic is the row-frame form (FrameF16 and
+// The fp16 tier's cell arithmetic is the frame form (LaneFrame and
 // FrameStrip below); this holds the encoding and the epilogue.
 template <> struct Lane<TIER_F16X2> {
     typedef h2 V;
@@ -299,27 +299,6 @@ struct LaneFrame {
     __device__ h2 k(int n) const {
         const _Float16 v = (_Float16)(float)(n * alpha);
         return h2{v, v};
-    }
-};
-
-// Constants of the packed wave-per-pair kernel's row frame (see intra2_pass).
-struct FrameF16 {
-    h2 nalpha;    // -alpha
-    h2 palpha;    // +alpha
-    h2 nu;        // alpha - beta
-    h2 rebase;    // -kFrameRows * alpha
-    int bias;     // alpha, added to every profile score
-    __device__ FrameF16(int alpha, int beta) {
-        alpha = min(alpha, kFrameFlagAlpha);
-        beta = min(beta, 2048);
-        const _Float16 na = (_Float16)(float)(-alpha), pa = (_Float16)(float)alpha;
-        const _Float16 u = (_Float16)(float)(alpha - beta);
-        const _Float16 rb = (_Float16)(float)(-kFrameRows * alpha);
-        nalpha = h2{na, na};
-        palpha = h2{pa, pa};
-        nu = h2{u, u};
-        rebase = h2{rb, rb};
-        bias = alpha;
     }
 };
 
@@ -863,46 +842,54 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 // advances two alignments.  The two halves read their substitution scores from
 // two profile rows; one v_perm per column pair packs them.
 //
-// It evaluates the row-frame form of the lane-per-subject fp16 tier.  Lane l
-// works on subject row t - l at step t, so the offset of that row is taken as
-// alpha * ((t mod kFrameRows) - l): it grows by alpha per step, so E needs no
-// decay, it is the same for every lane that handles the row (H and F cross to
-// lane l+1 one step later), and it drops by kFrameRows * alpha for every lane
-// at once at the end of each block of kFrameRows steps, outputs included.
-// Offsets span [-63 alpha, 32 alpha]; for alpha <= kFrameMaxAlpha every value
-// that can matter stays an exact fp16 integer with thr = 1920 - 33 alpha, and
-// a value below -2048 rounds to one that is still below the frame's zero.
-// Larger alpha flags every half for the exact recompute.  Pass boundaries are
-// stored as true values and converted on the way in and out.
+// It evaluates the frame form of the lane-per-subject fp16 tier (LaneFrame).
+// Lane l works on subject row t - l at step t, so the offset of that row is
+// taken as alpha * ((t mod kFrameRows) - l): it grows by alpha per step, so E
+// needs no decay, it is the same for every lane that handles the row (H and F
+// cross to lane l+1 one step later), and it drops by kFrameRows * alpha for
+// every lane at once at the end of each block of kFrameRows steps, outputs
+// included.  A lane's T columns start on a multiple of kFrameCols, so column
+// j of the lane adds alpha * (j mod kFrameCols) as in FrameStrip: F decays
+// once per group of columns (its hand-off to lane l+1 is in class 0), the E
+// floors and the two running bests are per class, and the profile carries
+// the diagonal's offset change per column class.  Offsets span
+// [-63 alpha, 35 alpha]; for alpha <= kFrameMaxAlpha every value that can
+// matter stays an exact fp16 integer with thr = 1920 - 36 alpha, and a value
+// below -2048 rounds to one that is still below the frame's zero.  Larger
+// alpha flags every half for the exact recompute.  Pass boundaries are stored
+// as true values and converted on the way in and out.
 // ---------------------------------------------------------------------------
 template <int T>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
-                                           const uint2 *pb, const FrameF16 &ops, h2 hdiag, h2 f,
-                                           h2 fl, h2 &best, h2 &hout, h2 &fout) {
+                                           const uint2 *pb, const LaneFrame &ops, h2 hdiag, h2 f,
+                                           const h2 (&FL)[kFrameCols], h2 (&B)[2], h2 &hout,
+                                           h2 &fout) {
+    static_assert(kFrameCols == 4 && T % kFrameCols == 0, "a lane holds whole column groups");
     // (low half from subject a's row, high half from subject b's row)
     uint32_t sv[T];
 #pragma unroll
     for (int j4 = 0; j4 < T / 4; ++j4) {
-        const uint2 A = pa[j4], B = pb[j4];
-        sv[4 * j4 + 0] = __builtin_amdgcn_perm(B.x, A.x, 0x05040100u);
-        sv[4 * j4 + 1] = __builtin_amdgcn_perm(B.x, A.x, 0x07060302u);
-        sv[4 * j4 + 2] = __builtin_amdgcn_perm(B.y, A.y, 0x05040100u);
-        sv[4 * j4 + 3] = __builtin_amdgcn_perm(B.y, A.y, 0x07060302u);
+        const uint2 A = pa[j4], Bv = pb[j4];
+        sv[4 * j4 + 0] = __builtin_amdgcn_perm(Bv.x, A.x, 0x05040100u);
+        sv[4 * j4 + 1] = __builtin_amdgcn_perm(Bv.x, A.x, 0x07060302u);
+        sv[4 * j4 + 2] = __builtin_amdgcn_perm(Bv.y, A.y, 0x05040100u);
+        sv[4 * j4 + 3] = __builtin_amdgcn_perm(Bv.y, A.y, 0x07060302u);
     }
     // The diagonal operand of column j+1 is taken from H[j] before H[j] is
     // overwritten, so each new H goes into the register of the old one.
     h2 d = hdiag + as_v<h2>(sv[0]);
-    h2 hp = d;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
         const h2 dn = j + 1 < T ? H[j] + as_v<h2>(sv[j + 1]) : d;
         const h2 h = FrameStrip<4>::max3(d, E[j], f);
         const h2 t = h + ops.nu;
-        E[j] = FrameStrip<4>::max3(E[j], t, fl);
-        f = __builtin_elementwise_maximum(f, t) + ops.nalpha;
+        E[j] = FrameStrip<4>::max3(E[j], t, FL[j & 3]);
+        f = __builtin_elementwise_maximum(f, t);
+        if ((j & 3) == 3) f += ops.ngroup;
         H[j] = h;
-        if (j & 1) best = FrameStrip<4>::max3(best, hp, h);
-        hp = h;
+        // (r, j) and (r - 1, j + 1) share an offset for even j; H[j + 1]
+        // still holds row r - 1
+        if (!(j & 1)) B[(j & 2) >> 1] = FrameStrip<4>::max3(B[(j & 2) >> 1], h, H[j + 1]);
         d = dn;
     }
     hout = H[T - 1];
@@ -910,7 +897,7 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
 }
 
 template <int T, bool HAS_IN, bool HAS_OUT>
-__device__ __forceinline__ void intra2_pass(const IntraArgs &a, const FrameF16 &ops,
+__device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame &ops,
                                             const uint16_t *prof, int RS, int32_t *wsc,
                                             const uint8_t *sa, const uint8_t *sb, int na, int nb,
                                             int pad, h2 &best_io) {
@@ -919,30 +906,40 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const FrameF16 &
     const int nblk = (n + 63) / 64;
     const int steps = HAS_OUT ? nblk * 64 + 63 : n + 63;
     const h2 pa2 = ops.palpha;
-    const float alpha = (float)ops.bias;
+    const float alpha = (float)ops.alpha;
+    constexpr int G = kFrameCols;
     // Offset of this lane at step 0, and the per-lane conversions of the
-    // lane-0 feeders (row consumed at step row: alpha * (row mod 32)) and of
-    // the collected last-lane outputs (row produced by lane 63 at step row+63).
+    // lane-0 feeders (row consumed at step row: alpha * (row mod 32); H comes
+    // from the previous pass's last column, class G - 1) and of the collected
+    // last-lane outputs (row produced by lane 63 at step row+63).
     const _Float16 o0 = (_Float16)(-alpha * lane);
     const _Float16 fc = (_Float16)(alpha * (lane & (kFrameRows - 1)));
+    const _Float16 fch = (_Float16)(alpha * ((lane & (kFrameRows - 1)) + G - 1));
     const _Float16 wc = (_Float16)(alpha * (((lane - 1) & (kFrameRows - 1)) - 63));
-    const h2 off0 = h2{o0, o0}, fconv = h2{fc, fc}, wconv = h2{wc, wc};
+    const _Float16 wch = (_Float16)(alpha * (((lane - 1) & (kFrameRows - 1)) - 63 + G - 1));
+    const h2 off0 = h2{o0, o0}, fconv = h2{fc, fc}, fconv_h = h2{fch, fch};
+    const h2 wconv = h2{wc, wc}, wconv_h = h2{wch, wch};
     h2 H[T], E[T];
 #pragma unroll
-    for (int j = 0; j < T; ++j) { H[j] = off0 + ops.nalpha; E[j] = off0; }
-    h2 fl = off0 + pa2;
-    h2 best = best_io + off0;
-    h2 hb_prev = off0 + ops.nalpha;
+    for (int j = 0; j < T; ++j) {
+        H[j] = off0 + ops.k((j & 3) - 1);
+        E[j] = off0 + ops.k(j & 3);
+    }
+    h2 FL[G];
+#pragma unroll
+    for (int c = 0; c < G; ++c) FL[c] = off0 + ops.k(c + 1);
+    h2 B[2] = {best_io + off0, off0 + ops.k(2)};
+    h2 hb_prev = off0 + ops.k(G - 2);
     // outputs handed to lane l+1 before step 0 stand for step -1 of lane l:
-    // true 0 at offset -alpha * (l + 1)
-    h2 hout = off0 + ops.nalpha, fout = off0 + ops.nalpha;
+    // true 0 at offset -alpha * (l + 1), plus the class offset of H's column
+    h2 hout = off0 + ops.k(G - 2), fout = off0 + ops.nalpha;
     int r = pad | (pad << 8);   // residue codes of both subjects, a in the low byte
     int cH = 0, cF = 0;
     auto feed = [&](int row, int &fr, int &fh, int &ff) {
         const int ra = row < na ? sa[row] : pad;
         const int rb = row < nb ? sb[row] : pad;
         fr = ra | (rb << 8);
-        h2 vh = fconv, vf = fconv;
+        h2 vh = fconv_h, vf = fconv;
         if (HAS_IN && row < n) {
             vh += as_v<h2>((uint32_t)wsc[2 * row]);
             vf += as_v<h2>((uint32_t)wsc[2 * row + 1]);
@@ -968,17 +965,19 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const FrameF16 &
             fF = shl1(fF, fF);
             const uint2 *pa = (const uint2 *)(prof + (r & 0xff) * RS + lane * T);
             const uint2 *pb = (const uint2 *)(prof + (r >> 8) * RS + lane * T);
-            intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, fl, best, hout, fout);
+            intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, FL, B, hout, fout);
             hb_prev = hin;
-            fl += pa2;
-            best += pa2;
+#pragma unroll
+            for (int c = 0; c < G; ++c) FL[c] += pa2;
+            B[0] += pa2;
+            B[1] += pa2;
             if (HAS_OUT) {
                 cH = shl1((int)as_u(hout), cH);
                 cF = shl1((int)as_u(fout), cF);
                 const int t = tb + u;
                 if ((t & 63) == 62 && t >= 126) {
                     const int row = t - 126 + lane;
-                    wsc[2 * row] = (int)as_u(as_v<h2>((uint32_t)cH) - wconv);
+                    wsc[2 * row] = (int)as_u(as_v<h2>((uint32_t)cH) - wconv_h);
                     wsc[2 * row + 1] = (int)as_u(as_v<h2>((uint32_t)cF) - wconv);
                 }
             }
@@ -989,20 +988,30 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const FrameF16 &
                 H[j] += ops.rebase;
                 E[j] += ops.rebase;
             }
-            fl += ops.rebase;
-            best += ops.rebase;
+#pragma unroll
+            for (int c = 0; c < G; ++c) FL[c] += ops.rebase;
+            B[0] += ops.rebase;
+            B[1] += ops.rebase;
             hb_prev += ops.rebase;
             hout += ops.rebase;
             fout += ops.rebase;
         }
     }
-    // best is at the offset of step `steps`
+    // The last step's odd columns (classes 1 and 3), at the offsets of B[0]
+    // and B[1] after that step.
+#pragma unroll
+    for (int j = 0; j < T; j += 4) {
+        B[0] = __builtin_elementwise_maximum(B[0], H[j + 1]);
+        B[1] = __builtin_elementwise_maximum(B[1], H[j + 3]);
+    }
+    // B[0] is at the offset of step `steps`, B[1] two alpha above it
     const _Float16 oe = (_Float16)(alpha * ((steps & (kFrameRows - 1)) - lane));
-    best_io = best - h2{oe, oe};
+    const h2 oe2 = h2{oe, oe};
+    best_io = __builtin_elementwise_maximum(B[0] - oe2, B[1] - (oe2 + ops.k(2)));
 }
 
 template <int T, int W>
-__global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
+__global__ void __launch_bounds__(W * 64, 4) intra2_kernel(IntraArgs a) {
     typedef Lane<TIER_F16X2> L;
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // fp16 entries per profile row (padded)
@@ -1033,8 +1042,8 @@ __global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
         const int npass = (a.qs.qlen[q] + PW - 1) / PW;
         const int8_t *qp = a.qs.qp[q];
         const int alpha = a.qs.gap[2 * q];
-        const FrameF16 ops(min(alpha, kFrameMaxAlpha), min(a.qs.gap[2 * q + 1], 2048));
-        const int thr = alpha > kFrameMaxAlpha ? 0 : frame_thr(a.thr, alpha);
+        const LaneFrame ops(min(alpha, kFrameMaxAlpha), a.qs.gap[2 * q + 1]);
+        const int thr = alpha > kFrameMaxAlpha ? 0 : lane_frame_thr(a.thr, alpha);
         h2 best = L::zero();
 
         for (int p = 0; p < npass; ++p) {
@@ -1042,7 +1051,8 @@ __global__ void __launch_bounds__(W * 64) intra2_kernel(IntraArgs a) {
             for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
                 const int r = e / PW, c = e - r * PW;
                 const int col = p * PW + c;
-                prof[r * RS + c] = L::enc((col < mp ? (int)qp[(size_t)r * mp + col] : 0) + ops.bias);
+                const int bias = col % kFrameCols == 0 ? ops.bias0 : ops.bias1;
+                prof[r * RS + c] = L::enc((col < mp ? (int)qp[(size_t)r * mp + col] : 0) + bias);
             }
             __syncthreads();
             if (n <= 0) continue;

@@ -369,24 +369,29 @@ def test_frame_model_needs_the_last_row_tail(orc):
                     tail=False)
 
 
-def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, init_out_shift=True):
-    """Row-frame fp16 arithmetic of the packed wave-per-pair kernel, replayed
-    step by step: `lanes` lanes of T query columns each (a pass covers
-    lanes * T columns), lane l computing subject row t - l at step t, H and F
-    of its last column handed to lane l+1 one step later, lane 0 fed from the
-    previous pass's boundary (stored as true values) or from true 0, the last
-    lane's outputs collected as true values for the next pass.  Values of the
-    row at lane l and step t sit at offset alpha * ((t mod rows) - l); every
-    carried value drops by rows * alpha at the end of each block of `rows`
-    steps.  Vectorised over pairs of equal shape (Q: (B, m), S: (B, n)).
+def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, G=4, init_out_shift=True,
+                       tail=True):
+    """Frame fp16 arithmetic of the packed wave-per-pair kernel, replayed step
+    by step: `lanes` lanes of T query columns each (a pass covers lanes * T
+    columns), lane l computing subject row t - l at step t, H and F of its last
+    column handed to lane l+1 one step later, lane 0 fed from the previous
+    pass's boundary (stored as true values) or from true 0, the last lane's
+    outputs collected as true values for the next pass.  Cell (row, column jj
+    of lane l) at step t sits at offset alpha * ((t mod rows) - l + (jj mod G)):
+    E needs no decay, F decays by G alpha once per group of G columns, and the
+    running best pairs (row, jj even) with (row - 1, jj + 1) into one register
+    per even class, the last step's odd columns taken at the end (`tail`).
+    Every carried value drops by rows * alpha at the end of each block of
+    `rows` steps.  Vectorised over pairs of equal shape (Q: (B, m), S: (B, n)).
     init_out_shift=False plants a wrong initial offset of the outputs handed
-    on before step 0 (used by the negative control)."""
+    on before step 0 (used by a negative control)."""
+    assert G % 2 == 0 and T % G == 0
     B, m = Q.shape
     n = S.shape[1]
     f16 = np.float16
     a = min(alpha, 28)
     b = min(beta, 2048)
-    nalpha, palpha, nu, rb = f16(-a), f16(a), f16(a - b), f16(-rows * a)
+    nalpha, palpha, nu, rb, ng = f16(-a), f16(a), f16(a - b), f16(-rows * a), f16(-G * a)
     A = M.shape[0]
     Mx = np.zeros((A + 1, A + 1), np.int64)
     Mx[:A, :A] = M
@@ -396,72 +401,88 @@ def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, init_out_sh
     Qp[:, :m] = Q
     nblk = (n + lanes - 1) // lanes
     L = np.arange(lanes)
+    cls = np.arange(T) % G
+    bias = np.where(cls == 0, (2 - G) * a, 2 * a)                      # per lane column
     best_true = np.zeros(B, f16)
     bound_h = bound_f = None         # true values per row from the previous pass
+    lanes_b = lambda v: np.broadcast_to(np.asarray(v, f16)[:, None], (lanes, B)).astype(f16).copy()
     with np.errstate(over="ignore", invalid="ignore"):
         for p in range(npass):
             has_in, has_out = p > 0, p + 1 < npass
             steps = nblk * lanes + lanes - 1 if has_out else n + lanes - 1
-            off0 = (-a * L).astype(f16)                           # (lanes,)
-            H = np.broadcast_to((off0 + nalpha)[:, None, None], (lanes, T, B)).astype(f16).copy()
-            E = np.broadcast_to(off0[:, None, None], (lanes, T, B)).astype(f16).copy()
-            fl = np.broadcast_to((off0 + palpha)[:, None], (lanes, B)).astype(f16).copy()
-            best = (best_true[None, :] + off0[:, None]).astype(f16)
-            hb_prev = np.broadcast_to((off0 + nalpha)[:, None], (lanes, B)).astype(f16).copy()
-            o = off0 + nalpha if init_out_shift else off0
-            hout = np.broadcast_to(o[:, None], (lanes, B)).astype(f16).copy()
-            fout = hout.copy()
+            off0 = (-a * L).astype(np.int64)                          # (lanes,)
+            H = np.stack([lanes_b(off0 + a * (cls[jj] - 1)) for jj in range(T)], axis=1)
+            E = np.stack([lanes_b(off0 + a * cls[jj]) for jj in range(T)], axis=1)
+            fl = [lanes_b(off0 + a * (1 + c)) for c in range(G)]
+            bests = {c: lanes_b(off0 + a * c) for c in range(0, G, 2)}
+            bests[0] = (best_true[None, :] + lanes_b(off0)).astype(f16)
+            hb_prev = lanes_b(off0 + a * (G - 2))
+            hout = lanes_b(off0 + a * (G - 2) if init_out_shift else off0 + a * (G - 1))
+            fout = lanes_b(off0 - a)
             rowcode = np.full((lanes, B), A, np.int64)
             new_h = np.zeros((max(nblk, 1) * lanes, B), f16)
             new_f = np.zeros((max(nblk, 1) * lanes, B), f16)
             for t in range(steps):
                 # lane 0 takes row t from the feeder, lane l the previous step's lane l-1
                 fr = S[:, t] if t < n else np.full(B, A, np.int64)
-                conv = f16(a * (t % rows))
+                conv = a * (t % rows)
                 if has_in and t < n:
-                    fh = (bound_h[t] + conv).astype(f16)
-                    ff = (bound_f[t] + conv).astype(f16)
+                    fh = (bound_h[t] + f16(conv + a * (G - 1))).astype(f16)
+                    ff = (bound_f[t] + f16(conv)).astype(f16)
                 else:
-                    fh = np.full(B, conv, f16)
-                    ff = fh.copy()
+                    fh = np.full(B, f16(conv + a * (G - 1)), f16)
+                    ff = np.full(B, f16(conv), f16)
                 rowcode = np.concatenate([fr[None, :], rowcode[:-1]])
                 hin = np.concatenate([fh[None, :], hout[:-1]])
                 fin = np.concatenate([ff[None, :], fout[:-1]])
                 # one row per lane
                 hdiag = hb_prev
                 f = fin
+                h_even = None
                 for jj in range(T):
+                    c = cls[jj]
                     col = p * PW + L * T + jj                          # (lanes,)
-                    s = (Mx[Qp[:, col].T, rowcode] + a).astype(f16)    # (lanes, B)
+                    s = (Mx[Qp[:, col].T, rowcode] + bias[jj]).astype(f16)   # (lanes, B)
                     hold = H[:, jj].copy()
                     h = np.maximum(np.maximum((hdiag + s).astype(f16), E[:, jj]), f)
                     tt = (h + nu).astype(f16)
-                    E[:, jj] = np.maximum(np.maximum(E[:, jj], tt), fl)
-                    f = (np.maximum(f, tt) + nalpha).astype(f16)
+                    E[:, jj] = np.maximum(np.maximum(E[:, jj], tt), fl[c])
+                    f = np.maximum(f, tt)
+                    if c == G - 1:
+                        f = (f + ng).astype(f16)
                     H[:, jj] = h
                     hdiag = hold
-                    best = np.maximum(best, h)
+                    if jj % 2 == 0:
+                        h_even = h
+                    else:
+                        bests[c - 1] = np.maximum(np.maximum(bests[c - 1], h_even), hold)
                 hout = H[:, T - 1].copy()
                 fout = f.copy()
                 hb_prev = hin
-                fl = (fl + palpha).astype(f16)
-                best = (best + palpha).astype(f16)
+                fl = [(x + palpha).astype(f16) for x in fl]
+                bests = {c: (x + palpha).astype(f16) for c, x in bests.items()}
                 # the last lane finished row t - (lanes - 1): store it as a true value
                 r_done = t - (lanes - 1)
                 if has_out and 0 <= r_done < new_h.shape[0]:
-                    offw = f16(a * ((t % rows) - (lanes - 1)))
-                    new_h[r_done] = (hout[-1] - offw).astype(f16)
-                    new_f[r_done] = (fout[-1] - offw).astype(f16)
+                    offw = a * ((t % rows) - (lanes - 1))
+                    new_h[r_done] = (hout[-1] - f16(offw + a * (G - 1))).astype(f16)
+                    new_f[r_done] = (fout[-1] - f16(offw)).astype(f16)
                 if (t + 1) % rows == 0:
                     H = (H + rb).astype(f16)
                     E = (E + rb).astype(f16)
-                    fl = (fl + rb).astype(f16)
-                    best = (best + rb).astype(f16)
+                    fl = [(x + rb).astype(f16) for x in fl]
+                    bests = {c: (x + rb).astype(f16) for c, x in bests.items()}
                     hb_prev = (hb_prev + rb).astype(f16)
                     hout = (hout + rb).astype(f16)
                     fout = (fout + rb).astype(f16)
-            oe = (a * ((steps % rows) - L)).astype(f16)
-            lane_best = (best - oe[:, None]).astype(f16)
+            if tail:
+                for jj in range(1, T, 2):
+                    bests[cls[jj] - 1] = np.maximum(bests[cls[jj] - 1], H[:, jj])
+            oe = a * ((steps % rows) - L)                               # (lanes,)
+            lane_best = None
+            for c, x in bests.items():
+                v = (x - lanes_b(oe + a * c)).astype(f16)
+                lane_best = v if lane_best is None else np.maximum(lane_best, v)
             best_true = lane_best.max(axis=0)
             bound_h, bound_f = new_h, new_f
     assert not np.isnan(best_true).any()
@@ -479,31 +500,53 @@ def check_intra2(orc, Q, S, M, alpha, beta, thr, **kw):
 
 
 @pytest.mark.parametrize("thr", [1920, 300, 20])
-def test_intra2_row_frame_schedule(orc, thr):
-    """Packed wave-per-pair schedule with 8 lanes of T = 2 columns (passes of
-    16 columns): one to three passes, subjects spanning several 32-step
-    periods and several blocks of lanes, penalties across the alpha range."""
-    rng = np.random.Generator(np.random.PCG64(thr + 5))
+@pytest.mark.parametrize("T,G", [(4, 4), (2, 2)])
+def test_intra2_row_frame_schedule(orc, thr, T, G):
+    """Packed wave-per-pair schedule with 8 lanes of T columns (passes of 8T
+    columns), column classes of G: one to three passes, subjects spanning
+    several 32-step periods and several blocks of lanes, penalties across the
+    alpha range."""
+    rng = np.random.Generator(np.random.PCG64(thr + 5 + T))
     A = 20
     M = rng.integers(-4, 12, size=(A, A)).astype(np.int8)
-    for m, n in [(5, 40), (16, 70), (37, 90)]:
+    for m, n in [(5, 40), (8 * T, 70), (20 * T + 5, 90)]:
         Q = rng.integers(0, A, size=(12, m)).astype(np.uint8)
         S = rng.integers(0, A, size=(12, n)).astype(np.uint8)
         S[:3, 10:10 + min(m, 30)] = Q[:3, :min(m, 30)]        # some high scores
         for alpha, beta in [(2, 12), (1, 3), (28, 40)]:
-            c = frame_ceiling(thr, alpha)
-            check_intra2(orc, Q, S, M, alpha, beta, c, T=2, lanes=8)
+            c = lane_ceiling(thr, alpha, G=G)
+            check_intra2(orc, Q, S, M, alpha, beta, c, T=T, lanes=8, G=G)
 
 
 def test_intra2_model_rejects_a_wrong_initial_offset(orc):
-    """Negative control: outputs handed on before step 0 at the step-0 offset
-    instead of one step earlier leave lanes starting from a true value of
-    alpha, and unflagged scores come out too high."""
+    """Negative control: H handed on before step 0 at one alpha above its
+    offset gives a lane's first column a diagonal of true alpha on subject
+    row 0.  Alignments planted to start there (row 0, lane 1's first column)
+    must come out too high."""
     rng = np.random.Generator(np.random.PCG64(77))
     A = 20
-    M = rng.integers(-4, 12, size=(A, A)).astype(np.int8)
+    M = np.full((A, A), -3, np.int8)
+    np.fill_diagonal(M, 40)
     Q = rng.integers(0, A, size=(12, 20)).astype(np.uint8)
     S = rng.integers(0, A, size=(12, 50)).astype(np.uint8)
-    check_intra2(orc, Q, S, M, 2, 12, 1854, T=2, lanes=8)
+    S[:, :16] = Q[:, 4:20]
+    check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8)
     with pytest.raises(AssertionError):
-        check_intra2(orc, Q, S, M, 2, 12, 1854, T=2, lanes=8, init_out_shift=False)
+        check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8, init_out_shift=False)
+
+
+def test_intra2_model_needs_the_last_step_tail(orc):
+    """The running best takes a lane's odd columns of row r at row r + 1; the
+    last lane meets its last real row at the last step.  Queries planted at
+    the end of subjects (best cell in the last lane's last column, last row):
+    without the closing step the model must come out wrong."""
+    rng = np.random.Generator(np.random.PCG64(19))
+    A = 5
+    M = np.full((A, A), -3, np.int8)
+    np.fill_diagonal(M, 40)
+    Q = rng.integers(0, A, size=(8, 32)).astype(np.uint8)       # 8 lanes x 4 columns: one pass
+    S = rng.integers(0, A, size=(8, 50)).astype(np.uint8)
+    S[:, 18:] = Q
+    check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8)
+    with pytest.raises(AssertionError):
+        check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8, tail=False)
