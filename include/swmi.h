@@ -74,9 +74,9 @@ typedef struct sw_db_opts {
 /* Lane tiers of the lane-per-subject kernel. */
 #define SW_TIER_AUTO  0
 #define SW_TIER_F16X2 1   /* two subjects per 32-bit lane, packed fp16 holding exact
-                             integers, values offset by up to 32 x alpha; exact while the
-                             best score < 1920 - 33 x alpha, else the pair is flagged and
-                             recomputed in int32 (every pair when alpha > 56).  The planner
+                             integers, values offset by up to 35 x alpha; exact while the
+                             best score < 1920 - 36 x alpha, else the pair is flagged and
+                             recomputed in int32 (every pair when alpha > 53).  The planner
                              uses it when alpha <= 28 and SW_TIER_I16X2 otherwise. */
 #define SW_TIER_I16X2 2   /* two subjects per lane, saturating int16; exact below 32767 */
 

@@ -266,7 +266,7 @@ Plan plan_for(const sw_db *db, int64_t max_qlen, int alpha) {
     Plan p;
     auto it = db->tuned.find(qlen_bucket(max_qlen));
     if (it != db->tuned.end()) p = it->second;
-    // The fp16 tier's ceiling falls by 33 per unit of alpha (row frame);
+    // The fp16 tier's ceiling falls by 36 per unit of alpha (frame offsets);
     // past kFrameMaxAlpha the int16 tier flags far fewer lanes.
     if (p.tier == TIER_F16X2 && alpha > kFrameMaxAlpha) p.tier = TIER_I16X2;
     if (db->opts.tier) p.tier = db->opts.tier;

@@ -465,7 +465,7 @@ struct FrameStrip {
 };
 
 // Occupancy the register budget is sized for (waves per SIMD).
-// The fp16 row frame needs a few more registers than 128 at strip 16.
+// The fp16 frame form needs a few more registers than 128 at strip 16.
 template <int T, int TIER> struct InterOcc {
     static constexpr int value = T <= 16 ? (TIER == TIER_F16X2 ? 3 : 4) : (T <= 32 ? 2 : 1);
 };
