@@ -495,12 +495,13 @@ struct PassBufs {
 // Enqueue one pass: counter reset (a fill kernel, safe under graph capture),
 // lane-per-subject kernel, wave-per-pair kernel on the long list, exact
 // recompute of flagged lanes.  Optional events bracket the first kernel.
-// With `overlap`, the long list runs on the database's second stream, launched
-// before the lane-per-subject kernel so its longest pairs start at once (the
-// other order measured slower and erratic), and joins before the recompute.
-// The long list's makespan is its longest pair; overlapped, the rest of the
-// GPU works through the lane-per-subject queue meanwhile (+3.4% on one query
-// against 2M subjects).
+// The long list's makespan is its longest pair, so it should start at once
+// and share the GPU with the lane-per-subject work:
+//  * L.fused_long: its items run first in the lane-per-subject kernel's own
+//    work queue (one launch; see fuse_ok);
+//  * otherwise, with `overlap`, it runs on the database's second stream,
+//    launched before the lane-per-subject kernel (the other order measured
+//    slower and erratic), and joins before the recompute.
 int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_t st,
                  hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr, bool overlap = false) {
     HIPX(launch_fill_i32(b.counters, 0, 4, st));
