@@ -51,6 +51,9 @@ class Oracle:
         lib.oracle_search_subset.restype = None
         lib.oracle_search_subset.argtypes = [u8p, i32, u8p, i64p, i64p, i64, i8p, i32, i32,
                                              i32, i32p, i32]
+        lib.oracle_sw_align.restype = i64
+        lib.oracle_sw_align.argtypes = [u8p, i32, u8p, i64, i8p, i32, i32, i32, i32p, i64p,
+                                        ctypes.POINTER(ctypes.c_uint32), i64]
         lib.oracle_max_threads.restype = i32
         lib.oracle_max_threads.argtypes = []
         self._lib = lib
@@ -74,6 +77,32 @@ class Oracle:
         return int(self._lib.oracle_sw_score(
             self._p(q, ctypes.c_uint8), len(q), self._p(s, ctypes.c_uint8), len(s),
             self._p(mat, ctypes.c_int8), a, int(alpha), int(beta)))
+
+    def sw_align(self, q, s, matrix, alpha: int, beta: int) -> dict:
+        """Optimal local alignment of ``q`` against ``s`` with traceback (see
+        ``oracle_sw_align`` for the tie rules).  Returns score, q_begin, q_end,
+        s_begin, s_end (0-based, inclusive; -1 when the score is 0) and ops, a
+        list of (op, length) runs: op 0 aligned pair, 1 query residue against a
+        gap, 2 subject residue against a gap."""
+        q = np.ascontiguousarray(q, dtype=np.uint8)
+        s = np.ascontiguousarray(s, dtype=np.uint8)
+        mat = np.ascontiguousarray(matrix, dtype=np.int8)
+        res = np.zeros(3, np.int32)
+        sres = np.zeros(2, np.int64)
+        cap = len(q) + len(s) + 1
+        ops = np.zeros(cap, np.uint32)
+        qq = q if len(q) else np.zeros(1, np.uint8)
+        ss = s if len(s) else np.zeros(1, np.uint8)
+        n_ops = int(self._lib.oracle_sw_align(
+            self._p(qq, ctypes.c_uint8), len(q), self._p(ss, ctypes.c_uint8), len(s),
+            self._p(mat, ctypes.c_int8), mat.shape[0], int(alpha), int(beta),
+            self._p(res, ctypes.c_int32), self._p(sres, ctypes.c_int64),
+            self._p(ops, ctypes.c_uint32), cap))
+        if n_ops < 0:
+            raise MemoryError("oracle_sw_align failed (%d)" % n_ops)
+        return {"score": int(res[0]), "q_begin": int(res[1]), "q_end": int(res[2]),
+                "s_begin": int(sres[0]), "s_end": int(sres[1]),
+                "ops": [(int(o & 3), int(o >> 2)) for o in ops[:n_ops]]}
 
     def search(self, q, residues, offsets, matrix, alpha: int, beta: int,
                nthreads: int = 0) -> np.ndarray:

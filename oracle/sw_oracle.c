@@ -132,6 +132,152 @@ void oracle_search_subset(const uint8_t *q, int32_t m,
     }
 }
 
+/* Optimal local alignment of one query against one subject, with traceback
+ * (the conclusion names alignment reconstruction as future work; the scores
+ * are those of Eq. 1 above, the choice among equal-scoring alignments is a
+ * reading of this implementation).  Readings:
+ *   - the alignment ends at the first cell, in the order i then j (subject row
+ *     outer, query column inner, as above), whose H equals the score;
+ *   - walking back from there, H takes its value from the diagonal before E
+ *     before F; E and F take theirs from the gap opening (H - beta) before the
+ *     extension (E or F - alpha);
+ *   - the alignment starts at the first diagonal step whose predecessor
+ *     H(i-1, j-1) is 0 (or on the boundary).
+ * Output: res[0] = score, res[1] = q_begin, res[2] = q_end; sres[0] =
+ * s_begin, sres[1] = s_end (0-based, inclusive; -1 when the score is 0).
+ * ops: runs in forward order, (length << 2) | op with op 0 = aligned pair,
+ * 1 = query residue against a gap, 2 = subject residue against a gap; every
+ * gap (one opening and its extensions) is its own run, aligned pairs in a
+ * row share one.  Returns the number of runs, -1 if memory runs out and -2
+ * if ops_cap is too small.  Keeps one byte per cell: n * m bytes. */
+int64_t oracle_sw_align(const uint8_t *q, int32_t m, const uint8_t *s, int64_t n,
+                        const int8_t *matrix, int32_t alphabet, int32_t alpha, int32_t beta,
+                        int32_t *res, int64_t *sres, uint32_t *ops, int64_t ops_cap)
+{
+    res[0] = 0;
+    res[1] = res[2] = -1;
+    sres[0] = sres[1] = -1;
+    if (m <= 0 || n <= 0)
+        return 0;
+    /* dir[(i-1) * m + (j-1)] for cell (i, j): bits 0-1 where H came from
+     * (0 diagonal, 1 E, 2 F), bit 2 H == 0, bit 3 E opened, bit 4 F opened */
+    uint8_t *dir = (uint8_t *)malloc((size_t)n * (size_t)m);
+    int32_t *h_row = (int32_t *)calloc((size_t)m + 1, sizeof(int32_t));
+    int32_t *e_row = (int32_t *)calloc((size_t)m + 1, sizeof(int32_t));
+    uint32_t *rev = (uint32_t *)malloc(((size_t)n + (size_t)m + 1) * sizeof(uint32_t));
+    if (!dir || !h_row || !e_row || !rev) {
+        free(dir);
+        free(h_row);
+        free(e_row);
+        free(rev);
+        return -1;
+    }
+    int32_t best = 0;
+    int64_t bi = 0, bj = 0;
+    for (int64_t i = 1; i <= n; ++i) {
+        const int32_t s_res = s[i - 1];
+        int32_t h_diag = 0, h_left = 0, f = 0;
+        for (int32_t j = 1; j <= m; ++j) {
+            const int32_t sbt = matrix[(int32_t)q[j - 1] * alphabet + s_res];
+            const int32_t e_ext = e_row[j] - alpha, e_open = h_row[j] - beta;
+            const int32_t e = imax(e_ext, e_open);
+            const int32_t f_ext = f - alpha, f_open = h_left - beta;
+            f = imax(f_ext, f_open);
+            const int32_t d = h_diag + sbt;
+            int32_t h = imax(imax(0, d), imax(e, f));
+            uint8_t code;
+            if (h == 0) code = 4;
+            else if (h == d) code = 0;
+            else if (h == e) code = 1;
+            else code = 2;
+            if (e_open >= e_ext) code |= 8;
+            if (f_open >= f_ext) code |= 16;
+            dir[(size_t)(i - 1) * (size_t)m + (size_t)(j - 1)] = code;
+            h_diag = h_row[j];
+            h_row[j] = h;
+            e_row[j] = e;
+            h_left = h;
+            if (h > best) {
+                best = h;
+                bi = i;
+                bj = j;
+            }
+        }
+    }
+    free(h_row);
+    free(e_row);
+    res[0] = best;
+    if (best == 0) {
+        free(dir);
+        free(rev);
+        return 0;
+    }
+    /* walk back: state 0 in H, 1 in E, 2 in F; ops collected in reverse */
+    int64_t i = bi, j = bj, nrev = 0;
+    int state = 0;
+    uint32_t run_op = 3, run_len = 0;
+    for (;;) {
+        const uint8_t code = dir[(size_t)(i - 1) * (size_t)m + (size_t)(j - 1)];
+        if (state == 0) {
+            const int src = code & 3;
+            if (src == 0) {
+                if (run_op == 0) {
+                    ++run_len;
+                } else {
+                    if (run_len) rev[nrev++] = (run_len << 2) | run_op;
+                    run_op = 0;
+                    run_len = 1;
+                }
+                const int at_start = i == 1 || j == 1 ||
+                                     (dir[(size_t)(i - 2) * (size_t)m + (size_t)(j - 2)] & 4);
+                if (at_start)
+                    break;
+                --i;
+                --j;
+            } else {
+                state = src;   /* 1: E, 2: F; the gap run starts here */
+                if (run_len) rev[nrev++] = (run_len << 2) | run_op;
+                run_op = src == 1 ? 2u : 1u;
+                run_len = 0;
+            }
+        } else if (state == 1) {   /* subject residue i against a gap */
+            ++run_len;
+            const int opened = (code >> 3) & 1;
+            --i;
+            if (opened) {
+                rev[nrev++] = (run_len << 2) | run_op;
+                run_op = 3;
+                run_len = 0;
+                state = 0;
+            }
+        } else {                   /* query residue j against a gap */
+            ++run_len;
+            const int opened = (code >> 4) & 1;
+            --j;
+            if (opened) {
+                rev[nrev++] = (run_len << 2) | run_op;
+                run_op = 3;
+                run_len = 0;
+                state = 0;
+            }
+        }
+    }
+    if (run_len) rev[nrev++] = (run_len << 2) | run_op;
+    free(dir);
+    res[1] = (int32_t)(j - 1);
+    res[2] = (int32_t)(bj - 1);
+    sres[0] = i - 1;
+    sres[1] = bi - 1;
+    if (nrev > ops_cap) {
+        free(rev);
+        return -2;
+    }
+    for (int64_t k = 0; k < nrev; ++k)
+        ops[k] = rev[nrev - 1 - k];
+    free(rev);
+    return nrev;
+}
+
 /* Number of threads OpenMP would use (1 without OpenMP). */
 int32_t oracle_max_threads(void)
 {

@@ -235,6 +235,104 @@ def check_search_driver(o, seed=16):
     return fails
 
 
+GOLDEN_ALIGN = os.path.join(os.path.dirname(__file__), "golden", "align_examples.txt")
+_ABC = {"A": 0, "B": 1, "C": 2}
+_OPS = {"M": 0, "I": 1, "D": 2}
+
+
+def load_golden_align():
+    import re
+    cases = []
+    with open(GOLDEN_ALIGN) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            (name, q, s, match, mismatch, alpha, beta, score, qb, qe, sb, se,
+             ops) = line.split()
+            M = np.full((3, 3), int(mismatch), np.int8)
+            np.fill_diagonal(M, int(match))
+            exp = {"score": int(score), "q_begin": int(qb), "q_end": int(qe),
+                   "s_begin": int(sb), "s_end": int(se),
+                   "ops": [(_OPS[op], int(k)) for k, op in re.findall(r"(\d+)([MID])", ops)]}
+            cases.append((name, np.array([_ABC[c] for c in q], np.uint8),
+                          np.array([_ABC[c] for c in s], np.uint8), M, int(alpha), int(beta),
+                          exp))
+    return cases
+
+
+def check_align_golden(o):
+    """Hand-derived alignments, including every tie the traceback rules decide."""
+    fails = []
+    for name, q, s, M, a, b, exp in load_golden_align():
+        got = o.sw_align(q, s, M, a, b)
+        if got != exp:
+            fails.append(f"align golden {name}: got {got}, expected {exp}")
+    return fails
+
+
+def _align_cases(seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cases = list(tiny_cases(n=120, seed=seed))
+    for _ in range(60):
+        A = int(rng.integers(2, 5))
+        M = rng.integers(-6, 8, size=(A, A)).astype(np.int8)
+        np.fill_diagonal(M, rng.integers(3, 9, size=A))
+        q = rng.integers(0, A, size=int(rng.integers(1, 13))).astype(np.uint8)
+        s = rng.integers(0, A, size=int(rng.integers(1, 13))).astype(np.uint8)
+        a = int(rng.integers(0, 4))
+        b = a + int(rng.integers(0, 6))
+        cases.append((q, s, M, a, b))
+    return cases
+
+
+def check_align_rescore(o):
+    """The alignment is an optimal local alignment: by the run-cost
+    definition it scores the Smith-Waterman score (itself pinned above), it
+    consumes exactly q[q_begin..q_end] and s[s_begin..s_end], and it begins and
+    ends with an aligned pair; the empty alignment exactly when the score is 0."""
+    fails = []
+    for q, s, M, a, b in _align_cases(21):
+        al = o.sw_align(q, s, M, a, b)
+        sc = o.sw_score(q, s, M, a, b)
+        if al["score"] != sc:
+            fails.append(f"align score {al['score']} != sw_score {sc}")
+            continue
+        if sc == 0:
+            if al["ops"] or al["q_begin"] != -1 or al["s_end"] != -1:
+                fails.append("score 0 but a non-empty alignment")
+            continue
+        cols, qi, sj = refs.alignment_columns(al)
+        if not (0 <= al["q_begin"] <= al["q_end"] < len(q) and 0 <= al["s_begin"] <= al["s_end"] < len(s)):
+            fails.append("alignment bounds outside the sequences")
+            continue
+        if (qi - 1, sj - 1) != (al["q_end"], al["s_end"]):
+            fails.append("alignment does not end at q_end, s_end")
+            continue
+        if refs.score_alignment(al, q, s, M, a, b) != sc:
+            fails.append(f"alignment rescored {refs.score_alignment(al, q, s, M, a, b)} != {sc}")
+        if not al["ops"] or al["ops"][0][0] != 0 or al["ops"][-1][0] != 0:
+            fails.append("alignment does not begin and end with an aligned pair")
+    return fails
+
+
+def check_align_end(o):
+    """The end cell is the first maximum of the cubic recurrence's table in
+    subject-then-query order (the end-cell reading)."""
+    fails = []
+    for q, s, M, a, b in _align_cases(22)[::2]:
+        V = refs.general_gap_table(q, s, M, a, b)
+        best = max([0] + [v for row in V for v in row])
+        al = o.sw_align(q, s, M, a, b)
+        if best == 0:
+            continue
+        first = min((sb, qa) for qa in range(1, len(q) + 1) for sb in range(1, len(s) + 1)
+                    if V[qa][sb] == best)
+        if (al["s_end"] + 1, al["q_end"] + 1) != first:
+            fails.append(f"end {(al['s_end'], al['q_end'])} != first maximum {first}")
+    return fails
+
+
 ALL_CHECKS = {
     "golden": check_golden,
     "orientation": check_orientation,
@@ -244,6 +342,9 @@ ALL_CHECKS = {
     "ungapped": check_ungapped,
     "invariants": check_invariants,
     "search_driver": check_search_driver,
+    "align_golden": check_align_golden,
+    "align_rescore": check_align_rescore,
+    "align_end": check_align_end,
 }
 
 

@@ -82,16 +82,16 @@ def brute_force(q, s, M, alpha, beta):
     return best
 
 
-def general_gap_dp(q, s, M, alpha, beta):
-    """Cubic local-alignment DP with gap cost g(k) = beta + (k-1)*alpha."""
+def general_gap_table(q, s, M, alpha, beta):
+    """Cubic local-alignment DP with gap cost g(k) = beta + (k-1)*alpha.
+    Returns V with V[a][b] = best score of a local alignment ending at query
+    residue a and subject residue b (1-based; 0 = none)."""
     m, n = len(q), len(s)
 
     def g(k):
         return beta + (k - 1) * alpha
 
-    # V[a][b]: best local alignment score ending at query a, subject b (0 = none).
     V = [[0] * (n + 1) for _ in range(m + 1)]
-    best = 0
     for a in range(1, m + 1):
         for b in range(1, n + 1):
             v = max(0, V[a - 1][b - 1] + int(M[int(q[a - 1])][int(s[b - 1])]))
@@ -100,8 +100,40 @@ def general_gap_dp(q, s, M, alpha, beta):
             for k in range(1, b + 1):          # run of k subject residues against gaps
                 v = max(v, V[a][b - k] - g(k))
             V[a][b] = v
-            best = max(best, v)
-    return best
+    return V
+
+
+def general_gap_dp(q, s, M, alpha, beta):
+    """Best score of the cubic recurrence (max over general_gap_table)."""
+    V = general_gap_table(q, s, M, alpha, beta)
+    return max([0] + [v for row in V for v in row])
+
+
+def alignment_columns(al):
+    """Columns of an alignment given as begin positions and (op, length) runs:
+    op 0 aligned pair, 1 query residue against a gap, 2 subject residue
+    against a gap."""
+    qi, sj = al["q_begin"], al["s_begin"]
+    cols = []
+    for op, k in al["ops"]:
+        for _ in range(k):
+            if op == 0:
+                cols.append(("M", qi, sj))
+                qi += 1
+                sj += 1
+            elif op == 1:
+                cols.append(("Q", qi))
+                qi += 1
+            else:
+                cols.append(("S", sj))
+                sj += 1
+    return cols, qi, sj
+
+
+def score_alignment(al, q, s, M, alpha, beta):
+    """Score of an alignment by the run-cost definition (as brute_force)."""
+    cols, _, _ = alignment_columns(al)
+    return _score_columns(cols, q, s, M, alpha, beta)
 
 
 def linear_gap_sw(q, s, M, d):

@@ -2,7 +2,9 @@
 
 Each mutant is the oracle's C source with one textual change, compiled to a
 temporary library on the CPU.  The list covers dropped terms, wrong signs,
-swapped penalties, a transposed matrix, wrong indices and a lost floor.
+swapped penalties, a transposed matrix, wrong indices and a lost floor, and
+in the traceback the end-cell and tie rules, the start condition and the
+gap kinds.
 """
 import os
 import subprocess
@@ -30,6 +32,17 @@ MUTANTS = {
     "best_last_column_only": ("if (h > best)", "if (h > best && j == m)"),
     "best_last_row_only": ("if (h > best)", "if (h > best && i == n)"),
     "query_off_by_one": ("q[j - 1] * alphabet", "q[j < m ? j : j - 1] * alphabet"),
+    # traceback (oracle_sw_align)
+    "align_end_at_last_max": ("if (h > best) {", "if (h >= best) {"),
+    "align_E_before_diag": ("else if (h == d) code = 0;\n            else if (h == e) code = 1;",
+                            "else if (h == e) code = 1;\n            else if (h == d) code = 0;"),
+    "align_F_before_diag": ("if (h == 0) code = 4;\n            else if (h == d) code = 0;",
+                            "if (h == 0) code = 4;\n            else if (h == f && h != e) code = 2;\n"
+                            "            else if (h == d) code = 0;"),
+    "align_extend_before_open": ("if (e_open >= e_ext) code |= 8;", "if (e_open > e_ext) code |= 8;"),
+    "align_runs_past_zero": ("(dir[(size_t)(i - 2) * (size_t)m + (size_t)(j - 2)] & 4)", "0"),
+    "align_gap_ops_swapped": ("run_op = src == 1 ? 2u : 1u;", "run_op = src == 1 ? 1u : 2u;"),
+    "align_F_open_uses_alpha": ("f_open = h_left - beta;", "f_open = h_left - alpha;"),
 }
 
 
