@@ -160,6 +160,47 @@ int sw_db_search_batch(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_
                        const sw_scoring *sc, int32_t k, int32_t *top_scores, int64_t *top_idx,
                        int32_t *all_scores, void *hip_stream);
 
+/* ---- alignment with traceback ---- */
+
+/* One optimal local alignment (see sw_db_align).  Positions are 0-based and
+ * inclusive; all four are -1 when the score is 0 (empty alignment). */
+typedef struct sw_alignment {
+    int32_t score;
+    int32_t q_begin, q_end;   /* query residues q_begin..q_end */
+    int32_t n_ops;            /* runs of this alignment in `ops` */
+    int64_t s_begin, s_end;   /* subject residues s_begin..s_end */
+    int64_t ops_offset;       /* index of its first run in `ops` */
+} sw_alignment;
+
+#define SW_OP_PAIR   0   /* a query residue aligned with a subject residue */
+#define SW_OP_QGAP   1   /* a query residue against a gap */
+#define SW_OP_SGAP   2   /* a subject residue against a gap */
+
+/* Optimal local alignments, with traceback, of one query against the listed
+ * database sequences (alignment reconstruction is the future work the
+ * conclusion names; scores are those of section II.A, Eq. 1, and equal
+ * sw_db_search's).  Among equal-scoring alignments the result is fixed:
+ *   - it ends at the first cell, subject position outer and query position
+ *     inner, whose H equals the score;
+ *   - walking back, H is taken from the diagonal before E (subject residue
+ *     against a gap) before F (query residue against a gap), and E and F from
+ *     the gap opening before the extension;
+ *   - it starts at the first diagonal step whose predecessor H is 0.
+ *   ids: n_ids database indices (repeats allowed); out: n_ids results, in order.
+ *   ops: runs in forward order, each (length << 2) | SW_OP_*; every gap (one
+ *        opening and its extensions) is its own run, aligned pairs in a row
+ *        share one.  Alignment k's runs are ops[out[k].ops_offset ..
+ *        + out[k].n_ops - 1], packed one after another.
+ *   ops_cap: length of ops.  The library needs sum over ids of (len + qlen)
+ *        (an upper bound); *ops_needed (if non-NULL) receives it, and a smaller
+ *        ops_cap fails with SW_EINVAL.
+ * Device memory: one byte per cell of the pairs aligned together (batches of
+ * up to 1 GiB; a single subject needing more than 16 GiB fails with
+ * SW_ENOMEM).  Synchronous on the database's own stream. */
+int sw_db_align(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring *sc,
+                const int64_t *ids, int32_t n_ids, sw_alignment *out, uint32_t *ops,
+                int64_t ops_cap, int64_t *ops_needed);
+
 /* Run the autotuner: for each query-length bucket of the given lengths, time
  * every candidate plan on a sample of this database's blocks, re-time the two
  * fastest on the whole database (best of two runs) and keep the faster.  If

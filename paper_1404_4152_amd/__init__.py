@@ -53,6 +53,12 @@ class sw_stats(ctypes.Structure):
                 ("fused_long", ctypes.c_int32)]
 
 
+class sw_alignment(ctypes.Structure):
+    _fields_ = [("score", ctypes.c_int32), ("q_begin", ctypes.c_int32), ("q_end", ctypes.c_int32),
+                ("n_ops", ctypes.c_int32), ("s_begin", ctypes.c_int64), ("s_end", ctypes.c_int64),
+                ("ops_offset", ctypes.c_int64)]
+
+
 class sw_server_opts(ctypes.Structure):
     _fields_ = [("memory_budget", ctypes.c_int64), ("max_active", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("chunk_groups", ctypes.c_int32),
@@ -82,6 +88,8 @@ SIGNATURES = {
     "sw_db_search_batch": (ctypes.c_int, [_vp, ctypes.c_int32, _u8p, _i64p, _P(sw_scoring),
                                           ctypes.c_int32, _i32p, _i64p, _i32p, _vp]),
     "sw_db_autotune": (ctypes.c_int, [_vp, _P(sw_scoring), _i32p, ctypes.c_int32, ctypes.c_char_p]),
+    "sw_db_align": (ctypes.c_int, [_vp, _u8p, ctypes.c_int64, _P(sw_scoring), _i64p, ctypes.c_int32,
+                                   _P(sw_alignment), _P(ctypes.c_uint32), ctypes.c_int64, _i64p]),
     "sw_server_start": (ctypes.c_int, [_vp, _P(sw_server_opts), _P(_vp)]),
     "sw_server_submit": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), ctypes.c_int32,
                                         _P(ctypes.c_uint64)]),
@@ -243,6 +251,37 @@ def sw_db_autotune(h, matrix, alpha, beta, qlens, cache_path=None):
                                        cache_path.encode() if cache_path else None))
 
 
+def sw_db_align(h, query, matrix, alpha, beta, ids):
+    """Optimal local alignments of ``query`` against the database sequences
+    ``ids``: a list of dicts with score, q_begin, q_end, s_begin, s_end and
+    ops, a list of (op, length) runs (op 0 aligned pair, 1 query residue
+    against a gap, 2 subject residue against a gap)."""
+    q = _u8(query)
+    sc, keep = make_scoring(matrix, alpha, beta)
+    idv = np.ascontiguousarray(ids, dtype=np.int64)
+    n = len(idv)
+    out = (sw_alignment * max(n, 1))()
+    need = ctypes.c_int64(0)
+    if n:
+        # a call with no room for runs reports the bound they may need
+        rc = lib().sw_db_align(h, _ptr(q, ctypes.c_uint8), len(q), ctypes.byref(sc),
+                               _ptr(idv, ctypes.c_int64), n, out, None, 0, ctypes.byref(need))
+        if rc != SW_EINVAL or need.value <= 0:
+            _check(rc)
+    ops = np.zeros(max(need.value, 1), np.uint32)
+    _check(lib().sw_db_align(h, _ptr(q, ctypes.c_uint8), len(q), ctypes.byref(sc),
+                             _ptr(idv, ctypes.c_int64), n, out, _ptr(ops, ctypes.c_uint32),
+                             need.value, ctypes.byref(need)))
+    res = []
+    for k in range(n):
+        o = out[k]
+        runs = ops[o.ops_offset:o.ops_offset + o.n_ops]
+        res.append({"score": int(o.score), "q_begin": int(o.q_begin), "q_end": int(o.q_end),
+                    "s_begin": int(o.s_begin), "s_end": int(o.s_end),
+                    "ops": [(int(x & 3), int(x >> 2)) for x in runs]})
+    return res
+
+
 def sw_server_start(h, memory_budget=0, max_active=0, queue_capacity=0, chunk_groups=0):
     o = sw_server_opts(memory_budget, max_active, queue_capacity, chunk_groups)
     s = _vp()
@@ -298,6 +337,9 @@ class Database:
 
     def search_batch(self, queries, matrix, alpha, beta, k, all_scores=False):
         return sw_db_search_batch(self.h, queries, matrix, alpha, beta, k, all_scores)
+
+    def align(self, query, matrix, alpha, beta, ids):
+        return sw_db_align(self.h, query, matrix, alpha, beta, ids)
 
     def set_opts(self, **kw):
         return sw_db_set_opts(self.h, **kw)

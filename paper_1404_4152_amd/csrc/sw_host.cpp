@@ -223,6 +223,8 @@ struct sw_db {
     // per-call workspaces (plain and batched searches)
     DevBuf w_stage, w_scores, w_counters, w_ovf, w_scr_inter, w_scr_intra, w_topk, w_top;
     HostBuf h_stage;
+    DevBuf w_al_meta, w_al_dir, w_al_ops, w_al_scr;   // sw_db_align workspaces
+    HostBuf h_al;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     std::mutex mu;
     sw_search_opts opts{};
@@ -1651,6 +1653,137 @@ int sw_db_search_batch(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_
     TRY(busy(db));
     return run_search(db, nq, q_res, q_off, sc, k, top_scores, top_idx, all_scores, nullptr,
                       (hipStream_t)hip_stream, 1, true);
+}
+
+// Alignment with traceback: direction bytes are kept for every cell of a
+// batch's pairs, so pairs go in batches of at most kAlignBatchBytes of them
+// (a single larger pair runs alone, up to kAlignMaxPairBytes).
+namespace {
+constexpr size_t kAlignBatchBytes = (size_t)1 << 30;
+constexpr size_t kAlignMaxPairBytes = (size_t)16 << 30;
+
+int align_pairs(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring *sc,
+                const int64_t *ids, int32_t n_ids, sw_alignment *out, uint32_t *ops) {
+    const int R = db->R;
+    const int32_t mpad = (int32_t)round_up(qlen, kQPad);
+    const int32_t ldq = (int32_t)round_up(qlen, 16);
+    hipStream_t st = db->stream;
+    const int64_t max_len_pad = intra_scratch_rows(db);
+    int64_t ops_pos = 0;
+    for (int32_t b0 = 0; b0 < n_ids;) {
+        // this batch: [b0, b1)
+        int32_t b1 = b0;
+        size_t dir_bytes = 0, ops_n = 0;
+        while (b1 < n_ids) {
+            const size_t pb = (size_t)db->len[ids[b1]] * (size_t)ldq;
+            if (pb > kAlignMaxPairBytes)
+                return fail(SW_ENOMEM, "alignment of subject %lld needs %zu bytes of traceback",
+                            (long long)ids[b1], pb);
+            if (b1 > b0 && dir_bytes + pb > kAlignBatchBytes) break;
+            dir_bytes += pb;
+            ops_n += (size_t)db->len[ids[b1]] + (size_t)qlen;
+            ++b1;
+        }
+        const int32_t nb = b1 - b0;
+        const size_t meta_bytes = (size_t)nb * (3 * 8 + 3 * 4 + 6 * 4) + (size_t)R * mpad + 256;
+        TRY(db->w_al_meta.reserve(meta_bytes));
+        TRY(db->h_al.reserve(meta_bytes));
+        TRY(db->w_al_dir.reserve(std::max<size_t>(dir_bytes, 16)));
+        TRY(db->w_al_ops.reserve(std::max<size_t>(ops_n * 4, 4)));
+        const int grid = (nb + kAlignWaves - 1) / kAlignWaves;
+        TRY(db->w_al_scr.reserve((size_t)grid * kAlignWaves * (size_t)max_len_pad * 8));
+        // host staging: ids, dir offsets, ops offsets (int64), then the profile
+        HIPX(hipStreamSynchronize(st));
+        uint8_t *h = db->h_al.as<uint8_t>();
+        int64_t *h_ids = (int64_t *)h, *h_doff = h_ids + nb, *h_ooff = h_doff + nb;
+        int8_t *h_prof = (int8_t *)(h_ooff + nb);
+        size_t d_acc = 0, o_acc = 0;
+        for (int32_t k = 0; k < nb; ++k) {
+            const int64_t id = ids[b0 + k];
+            h_ids[k] = id;
+            h_doff[k] = (int64_t)d_acc;
+            h_ooff[k] = (int64_t)o_acc;
+            d_acc += (size_t)db->len[id] * (size_t)ldq;
+            o_acc += (size_t)db->len[id] + (size_t)qlen;
+        }
+        write_profile(h_prof, query, qlen, mpad, sc, R);
+        const size_t stage = (size_t)nb * 24 + (size_t)R * mpad;
+        uint8_t *d = db->w_al_meta.as<uint8_t>();
+        HIPX(hipMemcpyAsync(d, h, stage, hipMemcpyHostToDevice, st));
+        int32_t *d_end = (int32_t *)(d + round_up((int64_t)stage, 16));
+        int32_t *d_out = d_end + 3 * (size_t)nb;
+        AlignArgs a{};
+        a.res = db->d_res.as<uint8_t>();
+        a.off = db->d_off.as<int64_t>();
+        a.ids = (const int64_t *)d;
+        a.n_pairs = nb;
+        a.qp = (const int8_t *)(d + (size_t)nb * 24);
+        a.mpad = mpad;
+        a.qlen = (int32_t)qlen;
+        a.ldq = ldq;
+        a.alpha = sc->alpha;
+        a.beta = sc->beta;
+        a.R = R;
+        a.dir = db->w_al_dir.as<uint8_t>();
+        a.dir_off = a.ids + nb;
+        a.pass_scratch = db->w_al_scr.as<int32_t>();
+        a.max_len_pad = max_len_pad;
+        a.end = d_end;
+        a.ops = db->w_al_ops.as<uint32_t>();
+        a.ops_off = a.ids + 2 * (size_t)nb;
+        a.out = d_out;
+        HIPX(launch_align(a, st));
+        // results: per pair 6 int32, then the runs of each pair
+        std::vector<int32_t> res((size_t)nb * 6);
+        HIPX(hipMemcpyAsync(res.data(), d_out, res.size() * 4, hipMemcpyDeviceToHost, st));
+        std::vector<uint32_t> runs(o_acc);
+        if (o_acc) HIPX(hipMemcpyAsync(runs.data(), a.ops, o_acc * 4, hipMemcpyDeviceToHost, st));
+        HIPX(hipStreamSynchronize(st));
+        for (int32_t k = 0; k < nb; ++k) {
+            const int32_t *r = &res[(size_t)k * 6];
+            if (r[5] < 0)
+                return fail(SW_EDEVICE, "traceback of subject %lld left its bounds",
+                            (long long)ids[b0 + k]);
+            sw_alignment &o = out[b0 + k];
+            o.score = r[0];
+            o.q_begin = r[1];
+            o.q_end = r[2];
+            o.s_begin = r[3];
+            o.s_end = r[4];
+            o.n_ops = r[5];
+            o.ops_offset = ops_pos;
+            std::memcpy(ops + ops_pos, runs.data() + h_ooff[k], (size_t)r[5] * 4);
+            ops_pos += r[5];
+        }
+        b0 = b1;
+    }
+    return SW_OK;
+}
+}  // namespace
+
+int sw_db_align(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring *sc,
+                const int64_t *ids, int32_t n_ids, sw_alignment *out, uint32_t *ops,
+                int64_t ops_cap, int64_t *ops_needed) {
+    g_err.clear();
+    if (!db) return fail(SW_EINVAL, "db is NULL");
+    TRY(validate_scoring(db, sc));
+    TRY(validate_query(db, query, qlen));
+    if (n_ids < 0 || (n_ids > 0 && (!ids || !out))) return fail(SW_EINVAL, "bad id list or output");
+    int64_t need = 0;
+    for (int32_t k = 0; k < n_ids; ++k) {
+        if (ids[k] < 0 || ids[k] >= db->n_seqs)
+            return fail(SW_EINVAL, "id %lld not in 0..%lld", (long long)ids[k],
+                        (long long)db->n_seqs - 1);
+        need += db->len[ids[k]] + qlen;
+    }
+    if (ops_needed) *ops_needed = need;
+    if (ops_cap < need || (need > 0 && !ops))
+        return fail(SW_EINVAL, "ops holds %lld runs, the alignments may need %lld", (long long)ops_cap,
+                    (long long)need);
+    std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
+    HIPX(hipSetDevice(db->device));
+    return align_pairs(db, query, qlen, sc, ids, n_ids, out, ops);
 }
 
 int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,

@@ -117,6 +117,29 @@ hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStre
 
 hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st);
 
+// Alignment with traceback for a list of subjects against one query.
+struct AlignArgs {
+    const uint8_t *res;      // all residues, caller order
+    const int64_t *off;      // n_seqs + 1 offsets
+    const int64_t *ids;      // n_pairs subject ids
+    int32_t n_pairs;
+    const int8_t *qp;        // query profile: R rows x mpad columns
+    int32_t mpad, qlen, ldq; // ldq: direction row stride, qlen rounded up to 16
+    int32_t alpha, beta, R;
+    uint8_t *dir;            // direction bytes; pair p's len x ldq block at dir + dir_off[p]
+    const int64_t *dir_off;
+    int32_t *pass_scratch;   // per (slot, wave): max_len_pad x 2 int32 (H, F of a pass boundary)
+    int64_t max_len_pad;
+    int32_t *end;            // per pair: score, end row, end column (forward kernel output)
+    uint32_t *ops;           // per pair: runs at ops + ops_off[p], capacity len + qlen
+    const int64_t *ops_off;
+    int32_t *out;            // per pair: score, q_begin, q_end, s_begin, s_end, n_ops
+};
+constexpr int kAlignT = 16;       // query columns per lane (1024 per pass)
+constexpr int kAlignWaves = 4;    // pairs per workgroup (they share the query profile)
+hipError_t launch_align(const AlignArgs &a, hipStream_t st);
+int align_lds_bytes(int R);
+
 // Top-k by (score desc, index asc) over rows of `n` scores, `nq` rows.
 struct TopkWork {
     uint32_t *hist;      // nq * 256

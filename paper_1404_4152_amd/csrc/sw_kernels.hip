@@ -1126,6 +1126,262 @@ hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStrea
 // ascending database index).  Exact radix select over the 32-bit scores in
 // four 8-bit passes, then an ordered gather of the ties at the threshold.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Alignment with traceback (the conclusion leaves alignment reconstruction to
+// future work).  Scores are Eq. 1's; among equal-scoring alignments:
+//   - the alignment ends at the first cell, subject row then query column,
+//     whose H equals the score;
+//   - walking back, H comes from the diagonal before E before F, and E and F
+//     from the gap opening (H - beta) before the extension;
+//   - it starts at the first diagonal step whose predecessor H is 0 (or on the
+//     boundary).
+// Forward pass: the systolic wave-per-pair schedule of intra_item, in int32
+// on the recurrence as written (E and F start at 0 and are not floored, so
+// every tie is decided on exact values), storing one direction byte per cell:
+// bits 0-1 the source of H (0 diagonal, 1 E, 2 F), bit 2 H == 0, bit 3 E
+// opened, bit 4 F opened.  A lane hands H and F of its last column to the
+// lane on its right, which computes F of its first column (and that cell's
+// bit) itself.  A lane's 16 columns are 16 bytes of a row whose stride is
+// qlen rounded up to 16, so each step stores one aligned 16-byte vector.
+// Each lane keeps its first maximum (within a pass rows and columns come in
+// order; across passes a tie keeps the smaller row); the wave reduces by
+// (score desc, row asc, column asc).
+// Traceback: one thread per pair walks back from the end cell, every read
+// bounds-checked.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
+    constexpr int T = kAlignT;
+    constexpr int PW = 64 * T;          // query columns per pass
+    constexpr int RS = PW + 8;          // int16 per profile row (padded)
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    int16_t *prof = (int16_t *)lds;
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int pad = a.R - 1;
+    const int pair = blockIdx.x * W + w;
+    const int64_t id = pair < a.n_pairs ? a.ids[pair] : -1;
+    const int n = id >= 0 ? (int)(a.off[id + 1] - a.off[id]) : 0;
+    const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
+    uint8_t *dir = a.dir + (id >= 0 ? a.dir_off[pair] : 0);
+    int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
+    const int npass = (a.qlen + PW - 1) / PW;
+    const int alpha = a.alpha, beta = a.beta;
+    int best = 0, bi = 0x7fffffff, bj = 0x7fffffff;
+
+    for (int p = 0; p < npass; ++p) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
+            const int r = e / PW, c = e - r * PW;
+            const int col = p * PW + c;
+            prof[r * RS + c] = col < a.qlen ? (int16_t)a.qp[(size_t)r * a.mpad + col] : (int16_t)0;
+        }
+        __syncthreads();
+        if (n <= 0) continue;
+        const bool has_in = p > 0, has_out = p + 1 < npass;
+        const int nblk = (n + 63) / 64;
+        const int steps = has_out ? nblk * 64 + 63 : n + 63;
+        const int col0 = p * PW + lane * T;             // first query column of this lane
+        const bool cols_in_row = col0 < a.ldq;          // its 16 bytes lie inside the row
+        int H[T], E[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
+        int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
+        // Feeders: lane k holds the data of subject row 64*b + k: its residue
+        // and H, F of the previous pass's last column (0 on the first pass).
+        int fR, fH, fF, nR, nH, nF;
+        {
+            const int row = lane;
+            fR = row < n ? s[row] : pad;
+            fH = (has_in && row < n) ? wsc[2 * row] : 0;
+            fF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+            const int row2 = 64 + lane;
+            nR = row2 < n ? s[row2] : pad;
+            nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
+            nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
+        }
+        for (int t = 0; t < steps; ++t) {
+            if (t > 0 && (t & 63) == 0) {
+                fR = nR; fH = nH; fF = nF;
+                const int row = t + 64 + lane;
+                nR = row < n ? s[row] : pad;
+                nH = (has_in && row < n) ? wsc[2 * row] : 0;
+                nF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+            }
+            r = shr1(fR, r);
+            const int hin = shr1(fH, hout);     // H(i, col0 - 1)
+            const int fin = shr1(fF, fout);     // F(i, col0 - 1)
+            fR = shl1(fR, fR);
+            fH = shl1(fH, fH);
+            fF = shl1(fF, fF);
+            const int i = t - lane;             // this lane's subject row at this step
+            const bool real_row = i >= 0;       // rows before 0 keep the zero boundary
+            const bool track = real_row && i < n;
+            const int16_t *pr = prof + r * RS + lane * T;
+            int hdiag = hb_prev, hleft = hin, fprev = fin;
+            uint32_t cw[T / 4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int j = 0; j < T; ++j) {
+                const int hup = H[j];
+                const int e_ext = E[j] - alpha, e_open = hup - beta;
+                const int e = max(e_ext, e_open);
+                const int f_ext = fprev - alpha, f_open = hleft - beta;
+                const int fv = max(f_ext, f_open);
+                const int d = hdiag + (int)pr[j];
+                const int h = max(max(0, d), max(e, fv));
+                uint32_t code = h == 0 ? 4u : (h == d ? 0u : (h == e ? 1u : 2u));
+                code |= (e_open >= e_ext ? 8u : 0u) | (f_open >= f_ext ? 16u : 0u);
+                cw[j >> 2] |= code << (8 * (j & 3));
+                if (track && col0 + j < a.qlen && (h > best || (h == best && i < bi))) {
+                    best = h;
+                    bi = i;
+                    bj = col0 + j;
+                }
+                hdiag = hup;
+                H[j] = real_row ? h : 0;
+                E[j] = real_row ? e : 0;
+                hleft = H[j];
+                fprev = real_row ? fv : 0;
+            }
+            hout = H[T - 1];
+            fout = fprev;
+            if (track && cols_in_row)
+                *(uint4 *)(dir + (size_t)i * (size_t)a.ldq + col0) = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+            hb_prev = hin;
+            if (has_out) {
+                cH = shl1(hout, cH);
+                cF = shl1(fout, cF);
+                if ((t & 63) == 62 && t >= 126) {
+                    const int row = t - 126 + lane;
+                    wsc[2 * row] = cH;
+                    wsc[2 * row + 1] = cF;
+                }
+            }
+        }
+    }
+    // (score desc, row asc, column asc) over the wave
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int ob = __shfl_xor(best, o, 64), oi = __shfl_xor(bi, o, 64), oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && (oi < bi || (oi == bi && oj < bj)))) {
+            best = ob;
+            bi = oi;
+            bj = oj;
+        }
+    }
+    if (lane == 0 && pair < a.n_pairs) {
+        a.end[3 * pair] = best;
+        a.end[3 * pair + 1] = bi;
+        a.end[3 * pair + 2] = bj;
+    }
+}
+
+__global__ void align_back_kernel(AlignArgs a) {
+    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pair >= a.n_pairs) return;
+    int32_t *out = a.out + 6 * (size_t)pair;
+    const int64_t id = a.ids[pair];
+    const int score = a.end[3 * pair];
+    out[0] = score;
+    out[1] = out[2] = out[3] = out[4] = -1;
+    out[5] = 0;
+    if (id < 0 || score <= 0) return;
+    const int n = (int)(a.off[id + 1] - a.off[id]), m = a.qlen;
+    const int end_i = a.end[3 * pair + 1], end_j = a.end[3 * pair + 2];
+    const uint8_t *dir = a.dir + a.dir_off[pair];
+    const size_t ld = (size_t)a.ldq;
+    uint32_t *ops = a.ops + a.ops_off[pair];
+    const int64_t cap = (int64_t)n + m;
+    int i = end_i, j = end_j, state = 0;
+    uint32_t run_op = 3, run_len = 0;
+    int64_t nrev = 0, guard = 0;
+    bool ok = true;
+    auto push = [&](uint32_t v) {
+        if (nrev < cap) ops[nrev++] = v;
+        else ok = false;
+    };
+    for (;;) {
+        // every move lowers i or j, and a step that only enters E or F is
+        // followed by a move: at most 2 (n + m) + 1 steps
+        if (i < 0 || j < 0 || i >= n || j >= m || ++guard > 2 * cap + 2) {
+            ok = false;
+            break;
+        }
+        const uint32_t code = dir[(size_t)i * ld + j];
+        if (state == 0) {
+            const uint32_t src = code & 3u;
+            if (src == 0) {
+                if (run_op == 0) {
+                    ++run_len;
+                } else {
+                    if (run_len) push((run_len << 2) | run_op);
+                    run_op = 0;
+                    run_len = 1;
+                }
+                if (i == 0 || j == 0 || (dir[(size_t)(i - 1) * ld + (j - 1)] & 4u)) break;
+                --i;
+                --j;
+            } else if (src == 1 || src == 2) {
+                if (run_len) push((run_len << 2) | run_op);
+                state = (int)src;
+                run_op = src == 1 ? 2u : 1u;
+                run_len = 0;
+            } else {
+                ok = false;
+                break;
+            }
+        } else if (state == 1) {   // subject residue i against a gap
+            ++run_len;
+            const bool opened = (code >> 3) & 1u;
+            --i;
+            if (opened) {
+                push((run_len << 2) | run_op);
+                run_op = 3;
+                run_len = 0;
+                state = 0;
+            }
+        } else {                   // query residue j against a gap
+            ++run_len;
+            const bool opened = (code >> 4) & 1u;
+            --j;
+            if (opened) {
+                push((run_len << 2) | run_op);
+                run_op = 3;
+                run_len = 0;
+                state = 0;
+            }
+        }
+    }
+    if (ok && run_len) push((run_len << 2) | run_op);
+    if (!ok) {
+        out[5] = -1;
+        return;
+    }
+    for (int64_t k = 0; k < nrev / 2; ++k) {
+        const uint32_t x = ops[k];
+        ops[k] = ops[nrev - 1 - k];
+        ops[nrev - 1 - k] = x;
+    }
+    out[1] = j;
+    out[2] = end_j;
+    out[3] = i;
+    out[4] = end_i;
+    out[5] = (int32_t)nrev;
+}
+
+int align_lds_bytes(int R) { return intra_lds_bytes(R, kAlignT); }
+
+hipError_t launch_align(const AlignArgs &a, hipStream_t st) {
+    if (a.n_pairs <= 0) return hipSuccess;
+    const int grid = (a.n_pairs + kAlignWaves - 1) / kAlignWaves;
+    hipLaunchKernelGGL((align_fwd_kernel<kAlignWaves>), dim3(grid), dim3(kAlignWaves * 64),
+                       align_lds_bytes(a.R), st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(align_back_kernel, dim3((a.n_pairs + 63) / 64), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
 __global__ void fill_i32_kernel(int32_t *p, int32_t v, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -1340,6 +1596,7 @@ hipError_t prepare_kernels() {
         (const void *)intra_kernel<8, 4>,  (const void *)intra_kernel<16, 4>,
         (const void *)intra2_kernel<4, 4>, (const void *)intra2_kernel<8, 4>,
         (const void *)intra2_kernel<16, 4>,
+        (const void *)align_fwd_kernel<kAlignWaves>,
     };
 #undef SWMI_FUSED
 #undef SWMI_K

@@ -72,7 +72,8 @@ def test_null_handle_calls(swmi):
     assert rc == swmi.SW_EINVAL
 
 
-STRUCTS = ["sw_scoring", "sw_db_opts", "sw_search_opts", "sw_stats", "sw_server_opts", "sw_req_stats"]
+STRUCTS = ["sw_scoring", "sw_db_opts", "sw_search_opts", "sw_stats", "sw_server_opts", "sw_req_stats",
+           "sw_alignment"]
 
 
 def test_binding_structs_match_the_header(tmp_path):
