@@ -143,6 +143,7 @@ def run_plain(args, swmi, sd, torch):
         log(f"[bench] step {i + 1}/{args.steps} done ({time.perf_counter() - t:.1f}s)")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    align = None if args.no_align else run_align(args, swmi, db, w, res, off, queries, M)
     db.close()
     gcups = cells_step * args.steps / dt / 1e9
     st0 = all_sts[0]
@@ -167,6 +168,8 @@ def run_plain(args, swmi, sd, torch):
                               (sum(s["kernel_ms"] for s in all_sts) / 1e3) / 1e9, 2),
         "recomputed_pairs_per_step": sum(s["recomputed_pairs"] for s in all_sts) // max(args.steps, 1),
     }
+    if align:
+        out["align_topk"] = align
     if inter:
         avg_launch_ms = sum(s["inter_ms"] for s in inter) / len(inter)
         ops_per_launch = OPS_PER_CELL * sum(s["inter_cells"] for s in inter) / len(inter)
@@ -179,6 +182,28 @@ def run_plain(args, swmi, sd, torch):
                            "traffic_unit": "bytes per launch", "kernel": "inter_kernel (f16x2)",
                            "ops_per_cell": OPS_PER_CELL, "avg_launch_ms": round(avg_launch_ms, 3)}
     return out, (w, res, off, queries, M)
+
+
+def run_align(args, swmi, db, w, res, off, queries, M):
+    """Alignment with traceback (sw_db_align) of every query's top-k hits:
+    the hits come from untimed searches; the timed region is the align calls
+    for all queries (forward and traceback kernels, their copies)."""
+    lens = np.diff(off)
+    hits = []
+    for q in queries:
+        _, ti = db.topk(q, M, w.alpha, w.beta, args.k)
+        hits.append(ti[ti >= 0])
+    db.align(queries[0], M, w.alpha, w.beta, hits[0])          # warm-up
+    cells = sum(int(lens[h].sum()) * len(q) for q, h in zip(queries, hits))
+    pairs = sum(len(h) for h in hits)
+    t = time.perf_counter()
+    for q, h in zip(queries, hits):
+        db.align(q, M, w.alpha, w.beta, h)
+    dt = time.perf_counter() - t
+    log(f"[bench] aligned the top-{args.k} of {len(queries)} queries in {dt * 1e3:.1f} ms")
+    return {"pairs": pairs, "cells": cells, "ms_per_query": round(dt / len(queries) * 1e3, 3),
+            "gcups": round(cells / dt / 1e9, 2),
+            "what": f"traceback of each query's top-{args.k} hits"}
 
 
 def run_batched(args, swmi, sd, torch):
@@ -297,6 +322,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (the reference "
