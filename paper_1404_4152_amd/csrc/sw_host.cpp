@@ -5,8 +5,9 @@
 // 128 (64 lanes x 2 packed halves) laid out interleaved for coalesced wave
 // loads, padded with a residue code that scores 0 (section III.B.1).  The
 // longest subjects, which would hold one lane for too long, form a long list
-// served by the wave-per-pair kernel, as does any database too small to fill
-// the GPU lane-per-subject.
+// served wave-per-pair (inside the lane-per-subject kernel's work queue when
+// it runs in int32), as does any database too small to fill the GPU
+// lane-per-subject.
 //
 // Search (stages i and iv): build the query profile (section III.B.2; row r
 // holds the scores of the whole query against residue r), run the kernels,
@@ -14,6 +15,10 @@
 // Batches of queries share one persistent launch (captured once per shape in
 // a HIP graph); the server keeps the database resident and coalesces the
 // requests in flight into shared passes over database chunks.
+//
+// Alignment with traceback (sw_db_align): the optimal local alignments of one
+// query against chosen database sequences, computed on the GPU with one
+// direction byte per cell and a walk back.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

@@ -16,7 +16,7 @@
 // that moves by alpha per subject row and per query column within groups of
 // four columns, and needs 5.75 (FrameStrip below).
 //
-// Two kernels:
+// Kernels:
 //  * inter_kernel: one lane per subject, two subjects per 32-bit lane in packed
 //    16-bit halves (the inter-sequence model of section III.B).  Subjects are
 //    length-sorted into groups of 128; a group is one wavefront.  Each lane
@@ -25,13 +25,18 @@
 //    row) goes through a per-wave boundary buffer.  This is the tiled SW
 //    computation of the conclusion.  The substitution scores of the strip sit
 //    in LDS as a pair profile P[a*R + b][j] = (M[q_j][a], M[q_j][b]) so that one
-//    dword read feeds both halves of a lane.
+//    dword read feeds both halves of a lane.  Its fused variants (TI > 0) first
+//    hand out the long list's wave-per-pair items from the same work queue.
 //  * intra_kernel: one wavefront per (query, subject) pair, int32 and exact
 //    (the intra-sequence model of section III.C, laid out as a systolic
 //    array along anti-diagonals rather than striped).  Lane l owns T query
 //    columns; at step t it computes subject row t - l; H and F of its last
 //    column move to lane l+1 with a DPP wave shift.  Serves long subjects,
 //    small databases and the exact recompute of flagged narrow-tier lanes.
+//  * intra2_kernel: the same schedule in packed fp16, two subjects per wave.
+//  * align_fwd_kernel / align_back_kernel: alignment with traceback (the same
+//    schedule in int32 storing a direction byte per cell, then a walk back).
+//  * topk_*: radix-select top-k of the score rows.
 //
 // Narrow-tier exactness.  A tier computes exactly while every intermediate
 // value is representable; it flags a lane whose best reaches the tier's
