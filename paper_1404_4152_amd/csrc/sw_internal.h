@@ -111,6 +111,8 @@ int inter_max_grid(int R, int tier, int strip, int waves, int ti = 0);
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);
+// LDS of the packed wave-per-pair kernel: the profile and one feed ring per wave.
+int intra2_lds_bytes(int R, int T, int waves);
 // Packed-fp16 wave-per-pair kernel: each wave aligns one query with two
 // subjects (item_ids holds 2 * waves ids per item).
 hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);

@@ -33,7 +33,9 @@
 //    columns; at step t it computes subject row t - l; H and F of its last
 //    column move to lane l+1 with a DPP wave shift.  Serves long subjects,
 //    small databases and the exact recompute of flagged narrow-tier lanes.
-//  * intra2_kernel: the same schedule in packed fp16, two subjects per wave.
+//  * intra2_kernel: the same schedule in packed fp16, two subjects per wave;
+//    each lane reads its subject residues, and lane 0 its incoming H and F,
+//    from a per-wave LDS ring instead of shifted feeder registers.
 //  * align_fwd_kernel / align_back_kernel: alignment with traceback (the same
 //    schedule in int32 storing a direction byte per cell, then a walk back).
 //  * topk_*: radix-select top-k of the score rows.
@@ -863,6 +865,10 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 // below -2048 rounds to one that is still below the frame's zero.  Larger
 // alpha flags every half for the exact recompute.  Pass boundaries are stored
 // as true values and converted on the way in and out.
+//
+// What enters at lane 0 (and the residue codes every lane needs) comes from a
+// per-wave LDS ring, filled once per 64 rows: at step t lane l reads entry
+// t - l, so no register shifts feeder values along the wave each step.
 // ---------------------------------------------------------------------------
 template <int T>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
@@ -901,20 +907,28 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
     fout = f;
 }
 
+// Per-wave LDS ring of the packed kernel: four arrays of kRing2 words (the
+// two subjects' residue codes, and the lane-0 feeds of H and F) covering the
+// previous and the current block of 64 subject rows.
+constexpr int kRing2 = 128;
+constexpr int kRing2Bytes = 4 * kRing2 * 4;
+
+int intra2_lds_bytes(int R, int T, int waves) { return intra_lds_bytes(R, T) + waves * kRing2Bytes; }
+
 template <int T, bool HAS_IN, bool HAS_OUT>
 __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame &ops,
                                             const uint16_t *prof, int RS, int32_t *wsc,
-                                            const uint8_t *sa, const uint8_t *sb, int na, int nb,
-                                            int pad, h2 &best_io) {
+                                            uint32_t *ring, const uint8_t *sa, const uint8_t *sb,
+                                            int na, int nb, int pad, h2 &best_io) {
     const int lane = threadIdx.x & 63;
-    const int n = na > nb ? na : nb;
+    const int n = __builtin_amdgcn_readfirstlane(na > nb ? na : nb);
     const int nblk = (n + 63) / 64;
     const int steps = HAS_OUT ? nblk * 64 + 63 : n + 63;
     const h2 pa2 = ops.palpha;
     const float alpha = (float)ops.alpha;
     constexpr int G = kFrameCols;
     // Offset of this lane at step 0, and the per-lane conversions of the
-    // lane-0 feeders (row consumed at step row: alpha * (row mod 32); H comes
+    // lane-0 feeds (row consumed at step row: alpha * (row mod 32); H comes
     // from the previous pass's last column, class G - 1) and of the collected
     // last-lane outputs (row produced by lane 63 at step row+63).
     const _Float16 o0 = (_Float16)(-alpha * lane);
@@ -938,38 +952,61 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     // outputs handed to lane l+1 before step 0 stand for step -1 of lane l:
     // true 0 at offset -alpha * (l + 1), plus the class offset of H's column
     h2 hout = off0 + ops.k(G - 2), fout = off0 + ops.nalpha;
-    int r = pad | (pad << 8);   // residue codes of both subjects, a in the low byte
     int cH = 0, cF = 0;
-    auto feed = [&](int row, int &fr, int &fh, int &ff) {
-        const int ra = row < na ? sa[row] : pad;
-        const int rb = row < nb ? sb[row] : pad;
-        fr = ra | (rb << 8);
+    // Lane l fills entry kRing2/2 + l of each ring array with row 64b + l of
+    // block b; entries [0, 64) keep block b - 1 (pad before row 0).  At step
+    // 64b + u lane l takes entry 64 + u - l: its own row's residue codes, and
+    // for lane 0 the H and F that enter the pass at that row.
+    auto feed = [&](int row, uint32_t &fa, uint32_t &fb, uint32_t &fh, uint32_t &ff) {
+        fa = row < na ? sa[row] : pad;
+        fb = row < nb ? sb[row] : pad;
         h2 vh = fconv_h, vf = fconv;
         if (HAS_IN && row < n) {
             vh += as_v<h2>((uint32_t)wsc[2 * row]);
             vf += as_v<h2>((uint32_t)wsc[2 * row + 1]);
         }
-        fh = (int)as_u(vh);
-        ff = (int)as_u(vf);
+        fh = as_u(vh);
+        ff = as_u(vf);
     };
-    int fR, fH, fF, nR, nH, nF;
-    feed(lane, fR, fH, fF);
-    feed(64 + lane, nR, nH, nF);
+    uint32_t cA, cB, cHf, cFf, nA, nB, nH, nF;
+    feed(lane, cA, cB, cHf, cFf);
+    feed(64 + lane, nA, nB, nH, nF);
+    ring[lane] = pad;
+    ring[kRing2 + lane] = pad;
+    ring[64 + lane] = cA;
+    ring[kRing2 + 64 + lane] = cB;
+    ring[2 * kRing2 + 64 + lane] = cHf;
+    ring[3 * kRing2 + 64 + lane] = cFf;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const uint32_t *rl = ring + 64 - lane;
     for (int tb = 0; tb < steps; tb += kFrameRows) {
         if (tb > 0 && (tb & 63) == 0) {
-            fR = nR; fH = nH; fF = nF;
-            feed(tb + 64 + lane, nR, nH, nF);
+            // block tb/64 - 1 moves down, block tb/64 comes in
+            ring[lane] = cA;
+            ring[kRing2 + lane] = cB;
+            ring[64 + lane] = nA;
+            ring[kRing2 + 64 + lane] = nB;
+            ring[2 * kRing2 + 64 + lane] = nH;
+            ring[3 * kRing2 + 64 + lane] = nF;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            cA = nA;
+            cB = nB;
+            feed(tb + 64 + lane, nA, nB, nH, nF);
         }
-        const int ue = steps - tb < kFrameRows ? steps - tb : kFrameRows;
+        const int ue =
+            __builtin_amdgcn_readfirstlane(steps - tb < kFrameRows ? steps - tb : kFrameRows);
+        const uint32_t *rb0 = rl + (tb & 63);
         for (int u = 0; u < ue; ++u) {
-            r = shr1(fR, r);
-            const h2 hin = as_v<h2>((uint32_t)shr1(fH, (int)as_u(hout)));
-            const h2 fin = as_v<h2>((uint32_t)shr1(fF, (int)as_u(fout)));
-            fR = shl1(fR, fR);
-            fH = shl1(fH, fH);
-            fF = shl1(fF, fF);
-            const uint2 *pa = (const uint2 *)(prof + (r & 0xff) * RS + lane * T);
-            const uint2 *pb = (const uint2 *)(prof + (r >> 8) * RS + lane * T);
+            const uint32_t *e = rb0 + u;
+            const h2 hin = as_v<h2>((uint32_t)shr1((int)e[2 * kRing2], (int)as_u(hout)));
+            const h2 fin = as_v<h2>((uint32_t)shr1((int)e[3 * kRing2], (int)as_u(fout)));
+            // residue codes are below 2^24, so the 24-bit multiply is exact
+            const uint2 *pa = (const uint2 *)(prof + (__umul24(e[0], RS) + lane * T));
+            const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRing2], RS) + lane * T));
             intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, FL, B, hout, fout);
             hb_prev = hin;
 #pragma unroll
@@ -1028,6 +1065,7 @@ __global__ void __launch_bounds__(W * 64, 4) intra2_kernel(IntraArgs a) {
     const int w = threadIdx.x >> 6;
     const int pad = a.R - 1;
     int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
+    uint32_t *ring = lds + (a.R * (PW + 8) * 2 + w * kRing2Bytes) / 4;   // after the profile
     const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
 
     for (;;) {
@@ -1063,11 +1101,11 @@ __global__ void __launch_bounds__(W * 64, 4) intra2_kernel(IntraArgs a) {
             if (n <= 0) continue;
             const bool has_in = p > 0, has_out = p + 1 < npass;
             if (has_in) {
-                if (has_out) intra2_pass<T, true, true>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
-                else intra2_pass<T, true, false>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
+                if (has_out) intra2_pass<T, true, true>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, true, false>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
             } else {
-                if (has_out) intra2_pass<T, false, true>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
-                else intra2_pass<T, false, false>(a, ops, prof, RS, wsc, sa, sb, na, nb, pad, best);
+                if (has_out) intra2_pass<T, false, true>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, false, false>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
             }
         }
 #pragma unroll
@@ -1097,7 +1135,7 @@ __global__ void __launch_bounds__(W * 64, 4) intra2_kernel(IntraArgs a) {
 
 template <int T, int W>
 static hipError_t launch_intra2_t(const IntraArgs &a, int grid, hipStream_t st) {
-    const int lds = intra_lds_bytes(a.R, T);
+    const int lds = intra2_lds_bytes(a.R, T, W);
     hipLaunchKernelGGL((intra2_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
     return hipGetLastError();
 }
