@@ -868,7 +868,8 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 //
 // What enters at lane 0 (and the residue codes every lane needs) comes from a
 // per-wave LDS ring, filled once per 64 rows: at step t lane l reads entry
-// t - l, so no register shifts feeder values along the wave each step.
+// t - l, so no register shifts feeder values along the wave each step.  The
+// last lane's outputs go through the same ring, read back once per 64 rows.
 // ---------------------------------------------------------------------------
 template <int T>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
@@ -907,11 +908,14 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
     fout = f;
 }
 
-// Per-wave LDS ring of the packed kernel: four arrays of kRing2 words (the
-// two subjects' residue codes, and the lane-0 feeds of H and F) covering the
-// previous and the current block of 64 subject rows.
-constexpr int kRing2 = 128;
-constexpr int kRing2Bytes = 4 * kRing2 * 4;
+// Per-wave LDS ring of the packed kernel, 638 words.  Entry x (0 <= x < 128)
+// of the residue-code arrays A and B covers row 64(b - 1) + x during block b
+// of 64 steps; the lane-0 feeds H and F keep only the current block (entries
+// 64..127); the output arrays OH and OF take entries 1..127.  Reads of
+// entries that an array does not keep land, in bounds, on another array and
+// only feed lanes whose value is discarded.
+constexpr int kRingA = 0, kRingB = 128, kRingH = 192, kRingF = 256, kRingOH = 383, kRingOF = 510;
+constexpr int kRing2Bytes = 638 * 4;
 
 int intra2_lds_bytes(int R, int T, int waves) { return intra_lds_bytes(R, T) + waves * kRing2Bytes; }
 
@@ -923,19 +927,21 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     const int lane = threadIdx.x & 63;
     const int n = __builtin_amdgcn_readfirstlane(na > nb ? na : nb);
     const int nblk = (n + 63) / 64;
-    const int steps = HAS_OUT ? nblk * 64 + 63 : n + 63;
+    // with outputs, the last block's collection needs step 64 * nblk + 63
+    const int steps = HAS_OUT ? nblk * 64 + 64 : n + 63;
     const h2 pa2 = ops.palpha;
     const float alpha = (float)ops.alpha;
     constexpr int G = kFrameCols;
     // Offset of this lane at step 0, and the per-lane conversions of the
     // lane-0 feeds (row consumed at step row: alpha * (row mod 32); H comes
     // from the previous pass's last column, class G - 1) and of the collected
-    // last-lane outputs (row produced by lane 63 at step row+63).
+    // last-lane outputs (lane l stores the row lane 63 produced at a step
+    // congruent to l mod 64, at offset alpha * ((l mod 32) - 63)).
     const _Float16 o0 = (_Float16)(-alpha * lane);
     const _Float16 fc = (_Float16)(alpha * (lane & (kFrameRows - 1)));
     const _Float16 fch = (_Float16)(alpha * ((lane & (kFrameRows - 1)) + G - 1));
-    const _Float16 wc = (_Float16)(alpha * (((lane - 1) & (kFrameRows - 1)) - 63));
-    const _Float16 wch = (_Float16)(alpha * (((lane - 1) & (kFrameRows - 1)) - 63 + G - 1));
+    const _Float16 wc = (_Float16)(alpha * ((lane & (kFrameRows - 1)) - 63));
+    const _Float16 wch = (_Float16)(alpha * ((lane & (kFrameRows - 1)) - 63 + G - 1));
     const h2 off0 = h2{o0, o0}, fconv = h2{fc, fc}, fconv_h = h2{fch, fch};
     const h2 wconv = h2{wc, wc}, wconv_h = h2{wch, wch};
     h2 H[T], E[T];
@@ -952,11 +958,12 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     // outputs handed to lane l+1 before step 0 stand for step -1 of lane l:
     // true 0 at offset -alpha * (l + 1), plus the class offset of H's column
     h2 hout = off0 + ops.k(G - 2), fout = off0 + ops.nalpha;
-    int cH = 0, cF = 0;
-    // Lane l fills entry kRing2/2 + l of each ring array with row 64b + l of
-    // block b; entries [0, 64) keep block b - 1 (pad before row 0).  At step
-    // 64b + u lane l takes entry 64 + u - l: its own row's residue codes, and
-    // for lane 0 the H and F that enter the pass at that row.
+    // Lane l fills entry 64 + l of each ring array with row 64b + l of block
+    // b.  At step 64b + u lane l reads entry 64 + u - l: its own row's
+    // residue codes and, for lane 0, the H and F that enter the pass at row
+    // 64b + u.  Every lane writes its outputs of that step to the same entry
+    // of OH and OF; entry u + 1 is lane 63's, and no later write of the block
+    // reaches it (lane l writes it at step u + 1 - 64 + l).
     auto feed = [&](int row, uint32_t &fa, uint32_t &fb, uint32_t &fh, uint32_t &ff) {
         fa = row < na ? sa[row] : pad;
         fb = row < nb ? sb[row] : pad;
@@ -971,25 +978,25 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     uint32_t cA, cB, cHf, cFf, nA, nB, nH, nF;
     feed(lane, cA, cB, cHf, cFf);
     feed(64 + lane, nA, nB, nH, nF);
-    ring[lane] = pad;
-    ring[kRing2 + lane] = pad;
-    ring[64 + lane] = cA;
-    ring[kRing2 + 64 + lane] = cB;
-    ring[2 * kRing2 + 64 + lane] = cHf;
-    ring[3 * kRing2 + 64 + lane] = cFf;
+    ring[kRingA + lane] = pad;
+    ring[kRingB + lane] = pad;
+    ring[kRingA + 64 + lane] = cA;
+    ring[kRingB + 64 + lane] = cB;
+    ring[kRingH + 64 + lane] = cHf;
+    ring[kRingF + 64 + lane] = cFf;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const uint32_t *rl = ring + 64 - lane;
+    uint32_t *rl = ring + 64 - lane;
     for (int tb = 0; tb < steps; tb += kFrameRows) {
         if (tb > 0 && (tb & 63) == 0) {
             // block tb/64 - 1 moves down, block tb/64 comes in
-            ring[lane] = cA;
-            ring[kRing2 + lane] = cB;
-            ring[64 + lane] = nA;
-            ring[kRing2 + 64 + lane] = nB;
-            ring[2 * kRing2 + 64 + lane] = nH;
-            ring[3 * kRing2 + 64 + lane] = nF;
+            ring[kRingA + lane] = cA;
+            ring[kRingB + lane] = cB;
+            ring[kRingA + 64 + lane] = nA;
+            ring[kRingB + 64 + lane] = nB;
+            ring[kRingH + 64 + lane] = nH;
+            ring[kRingF + 64 + lane] = nF;
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -999,14 +1006,14 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
         }
         const int ue =
             __builtin_amdgcn_readfirstlane(steps - tb < kFrameRows ? steps - tb : kFrameRows);
-        const uint32_t *rb0 = rl + (tb & 63);
+        uint32_t *rb0 = rl + (tb & 63);
         for (int u = 0; u < ue; ++u) {
-            const uint32_t *e = rb0 + u;
-            const h2 hin = as_v<h2>((uint32_t)shr1((int)e[2 * kRing2], (int)as_u(hout)));
-            const h2 fin = as_v<h2>((uint32_t)shr1((int)e[3 * kRing2], (int)as_u(fout)));
+            uint32_t *e = rb0 + u;
+            const h2 hin = as_v<h2>((uint32_t)shr1((int)e[kRingH], (int)as_u(hout)));
+            const h2 fin = as_v<h2>((uint32_t)shr1((int)e[kRingF], (int)as_u(fout)));
             // residue codes are below 2^24, so the 24-bit multiply is exact
-            const uint2 *pa = (const uint2 *)(prof + (__umul24(e[0], RS) + lane * T));
-            const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRing2], RS) + lane * T));
+            const uint2 *pa = (const uint2 *)(prof + (__umul24(e[kRingA], RS) + lane * T));
+            const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRingB], RS) + lane * T));
             intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, FL, B, hout, fout);
             hb_prev = hin;
 #pragma unroll
@@ -1014,14 +1021,22 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
             B[0] += pa2;
             B[1] += pa2;
             if (HAS_OUT) {
-                cH = shl1((int)as_u(hout), cH);
-                cF = shl1((int)as_u(fout), cF);
-                const int t = tb + u;
-                if ((t & 63) == 62 && t >= 126) {
-                    const int row = t - 126 + lane;
-                    wsc[2 * row] = (int)as_u(as_v<h2>((uint32_t)cH) - wconv_h);
-                    wsc[2 * row + 1] = (int)as_u(as_v<h2>((uint32_t)cF) - wconv);
-                }
+                e[kRingOH] = as_u(hout);
+                e[kRingOF] = as_u(fout);
+            }
+        }
+        if (HAS_OUT && (tb & 63) == 32) {
+            // the block's last step t = tb + 31 has passed; entries 1..64 hold
+            // lane 63's rows t - 126 .. t - 63 (steps with outputs run whole
+            // blocks of 64)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int row = tb + 31 - 126 + lane;
+            const uint32_t oh = ring[kRingOH + 1 + lane], of = ring[kRingOF + 1 + lane];
+            if (row >= 0 && row < n) {
+                wsc[2 * row] = (int)as_u(as_v<h2>(oh) - wconv_h);
+                wsc[2 * row + 1] = (int)as_u(as_v<h2>(of) - wconv);
             }
         }
         if (ue == kFrameRows) {
