@@ -871,11 +871,15 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 // t - l, so no register shifts feeder values along the wave each step.  The
 // last lane's outputs go through the same ring, read back once per 64 rows.
 // ---------------------------------------------------------------------------
-template <int T>
+// Steps of the packed kernel run in groups of kGrp2; row X of a group takes,
+// in column class c, the floor FW[X + c].
+constexpr int kGrp2 = 4;
+
+template <int T, int X>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
                                            const uint2 *pb, const LaneFrame &ops, h2 hdiag, h2 f,
-                                           const h2 (&FL)[kFrameCols], h2 (&B)[2], h2 &hout,
-                                           h2 &fout) {
+                                           const h2 (&FW)[kFrameCols + kGrp2 - 1], h2 (&B)[2],
+                                           h2 &hout, h2 &fout) {
     static_assert(kFrameCols == 4 && T % kFrameCols == 0, "a lane holds whole column groups");
     // (low half from subject a's row, high half from subject b's row)
     uint32_t sv[T];
@@ -895,7 +899,7 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
         const h2 dn = j + 1 < T ? H[j] + as_v<h2>(sv[j + 1]) : d;
         const h2 h = FrameStrip<4>::max3(d, E[j], f);
         const h2 t = h + ops.nu;
-        E[j] = FrameStrip<4>::max3(E[j], t, FL[j & 3]);
+        E[j] = FrameStrip<4>::max3(E[j], t, FW[X + (j & 3)]);
         f = __builtin_elementwise_maximum(f, t);
         if ((j & 3) == 3) f += ops.ngroup;
         H[j] = h;
@@ -927,9 +931,11 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     const int lane = threadIdx.x & 63;
     const int n = __builtin_amdgcn_readfirstlane(na > nb ? na : nb);
     const int nblk = (n + 63) / 64;
-    // with outputs, the last block's collection needs step 64 * nblk + 63
-    const int steps = HAS_OUT ? nblk * 64 + 64 : n + 63;
-    const h2 pa2 = ops.palpha;
+    // with outputs, the last block's collection needs step 64 * nblk + 63;
+    // steps run in whole groups (past the last row every lane reads pad
+    // rows, whose zero scores raise no best)
+    const int steps = HAS_OUT ? nblk * 64 + 64 : (n + 63 + kGrp2 - 1) / kGrp2 * kGrp2;
+    const h2 pa2 = ops.palpha, pag = ops.k(kGrp2);
     const float alpha = (float)ops.alpha;
     constexpr int G = kFrameCols;
     // Offset of this lane at step 0, and the per-lane conversions of the
@@ -950,9 +956,11 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
         H[j] = off0 + ops.k((j & 3) - 1);
         E[j] = off0 + ops.k(j & 3);
     }
-    h2 FL[G];
+    // E floors (true 0) of the steps of a group: step x of the group, class
+    // c, is at FW[x + c]; the window moves by kGrp2 * alpha per group
+    h2 FW[G + kGrp2 - 1];
 #pragma unroll
-    for (int c = 0; c < G; ++c) FL[c] = off0 + ops.k(c + 1);
+    for (int i = 0; i < G + kGrp2 - 1; ++i) FW[i] = off0 + ops.k(i + 1);
     h2 B[2] = {best_io + off0, off0 + ops.k(2)};
     h2 hb_prev = off0 + ops.k(G - 2);
     // outputs handed to lane l+1 before step 0 stand for step -1 of lane l:
@@ -1007,23 +1015,31 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
         const int ue =
             __builtin_amdgcn_readfirstlane(steps - tb < kFrameRows ? steps - tb : kFrameRows);
         uint32_t *rb0 = rl + (tb & 63);
-        for (int u = 0; u < ue; ++u) {
-            uint32_t *e = rb0 + u;
-            const h2 hin = as_v<h2>((uint32_t)shr1((int)e[kRingH], (int)as_u(hout)));
-            const h2 fin = as_v<h2>((uint32_t)shr1((int)e[kRingF], (int)as_u(fout)));
-            // residue codes are below 2^24, so the 24-bit multiply is exact
-            const uint2 *pa = (const uint2 *)(prof + (__umul24(e[kRingA], RS) + lane * T));
-            const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRingB], RS) + lane * T));
-            intra2_row<T>(H, E, pa, pb, ops, hb_prev, fin, FL, B, hout, fout);
-            hb_prev = hin;
+        for (int u = 0; u < ue; u += kGrp2) {
 #pragma unroll
-            for (int c = 0; c < G; ++c) FL[c] += pa2;
-            B[0] += pa2;
-            B[1] += pa2;
-            if (HAS_OUT) {
-                e[kRingOH] = as_u(hout);
-                e[kRingOF] = as_u(fout);
+            for (int x = 0; x < kGrp2; ++x) {
+                uint32_t *e = rb0 + u + x;
+                const h2 hin = as_v<h2>((uint32_t)shr1((int)e[kRingH], (int)as_u(hout)));
+                const h2 fin = as_v<h2>((uint32_t)shr1((int)e[kRingF], (int)as_u(fout)));
+                // residue codes are below 2^24, so the 24-bit multiply is exact
+                const uint2 *pa = (const uint2 *)(prof + (__umul24(e[kRingA], RS) + lane * T));
+                const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRingB], RS) + lane * T));
+                switch (x) {
+                case 0: intra2_row<T, 0>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 1: intra2_row<T, 1 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 2: intra2_row<T, 2 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                default: intra2_row<T, 3 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                }
+                hb_prev = hin;
+                B[0] += pa2;
+                B[1] += pa2;
+                if (HAS_OUT) {
+                    e[kRingOH] = as_u(hout);
+                    e[kRingOF] = as_u(fout);
+                }
             }
+#pragma unroll
+            for (int i = 0; i < G + kGrp2 - 1; ++i) FW[i] += pag;
         }
         if (HAS_OUT && (tb & 63) == 32) {
             // the block's last step t = tb + 31 has passed; entries 1..64 hold
@@ -1046,7 +1062,7 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
                 E[j] += ops.rebase;
             }
 #pragma unroll
-            for (int c = 0; c < G; ++c) FL[c] += ops.rebase;
+            for (int i = 0; i < G + kGrp2 - 1; ++i) FW[i] += ops.rebase;
             B[0] += ops.rebase;
             B[1] += ops.rebase;
             hb_prev += ops.rebase;
