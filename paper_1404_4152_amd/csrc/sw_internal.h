@@ -137,10 +137,8 @@ struct AlignArgs {
     const int64_t *ops_off;
     int32_t *out;            // per pair: score, q_begin, q_end, s_begin, s_end, n_ops
 };
-constexpr int kAlignT = 16;       // query columns per lane (1024 per pass)
 constexpr int kAlignWaves = 4;    // pairs per workgroup (they share the query profile)
 hipError_t launch_align(const AlignArgs &a, hipStream_t st);
-int align_lds_bytes(int R);
 
 // Top-k by (score desc, index asc) over rows of `n` scores, `nq` rows.
 struct TopkWork {

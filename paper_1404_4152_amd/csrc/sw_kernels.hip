@@ -1223,9 +1223,72 @@ hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStrea
 // Traceback: one thread per pair walks back from the end cell, every read
 // bounds-checked.
 // ---------------------------------------------------------------------------
-template <int W>
+// One subject row of a lane's T columns in the forward pass.  FILL: a step
+// in which lanes before row 0 keep the zero boundary (the first 63).  Each
+// lane keeps the first strict maximum of the pass in its own (row, column)
+// order, as (step, column); cells outside the subject or the query score 0 on
+// their diagonal and gap moves only lower a value, so none of them exceeds
+// the value of a real cell that precedes it.
+template <int T, bool FILL>
+__device__ __forceinline__ void align_row(const AlignArgs &a, int (&H)[T], int (&E)[T],
+                                          const int16_t *pr, int t, int i, int hdiag, int hleft,
+                                          int fprev, int &pbest, int &pt, int &pj, uint32_t (&cw)[T / 4],
+                                          int &hout, int &fout) {
+    static_assert(T % 4 == 0, "a lane stores whole 32-bit direction words");
+    // T int16 scores, read as T / 2 dwords; sign extension folds into the adds
+    uint32_t pw[T / 2];
+    if constexpr (T >= 8) {
+#pragma unroll
+        for (int k = 0; k < T / 8; ++k) {
+            const uint4 v = ((const uint4 *)pr)[k];
+            pw[4 * k] = v.x;
+            pw[4 * k + 1] = v.y;
+            pw[4 * k + 2] = v.z;
+            pw[4 * k + 3] = v.w;
+        }
+    } else {
+        const uint2 v = *(const uint2 *)pr;
+        pw[0] = v.x;
+        pw[1] = v.y;
+    }
+    const bool real_row = i >= 0;
+#pragma unroll
+    for (int k = 0; k < T / 4; ++k) cw[k] = 0;
+#pragma unroll
+    for (int j = 0; j < T; ++j) {
+        const int sc = (j & 1) ? ((int)pw[j >> 1] >> 16) : (int)(int16_t)(pw[j >> 1] & 0xffffu);
+        const int hup = H[j];
+        const int e_ext = E[j] - a.alpha, e_open = hup - a.beta;
+        const int e = max(e_ext, e_open);
+        const int f_ext = fprev - a.alpha, f_open = hleft - a.beta;
+        const int fv = max(f_ext, f_open);
+        const int d = hdiag + sc;
+        const int h = max(max(0, d), max(e, fv));
+        uint32_t code = h == 0 ? 4u : (h == d ? 0u : (h == e ? 1u : 2u));
+        code |= (e_open >= e_ext ? 8u : 0u) | (f_open >= f_ext ? 16u : 0u);
+        cw[j >> 2] |= code << (8 * (j & 3));
+        const bool gt = h > pbest;
+        pbest = gt ? h : pbest;
+        pt = gt ? t : pt;
+        pj = gt ? j : pj;
+        hdiag = hup;
+        if (FILL) {
+            H[j] = real_row ? h : 0;
+            E[j] = real_row ? e : 0;
+            fprev = real_row ? fv : 0;
+        } else {
+            H[j] = h;
+            E[j] = e;
+            fprev = fv;
+        }
+        hleft = H[j];
+    }
+    hout = H[T - 1];
+    fout = fprev;
+}
+
+template <int T, int W>
 __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
-    constexpr int T = kAlignT;
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // int16 per profile row (padded)
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -1240,7 +1303,6 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
     uint8_t *dir = a.dir + (id >= 0 ? a.dir_off[pair] : 0);
     int32_t *wsc = a.pass_scratch + (size_t)(blockIdx.x * W + w) * (size_t)a.max_len_pad * 2;
     const int npass = (a.qlen + PW - 1) / PW;
-    const int alpha = a.alpha, beta = a.beta;
     int best = 0, bi = 0x7fffffff, bj = 0x7fffffff;
 
     for (int p = 0; p < npass; ++p) {
@@ -1256,11 +1318,12 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
         const int nblk = (n + 63) / 64;
         const int steps = has_out ? nblk * 64 + 63 : n + 63;
         const int col0 = p * PW + lane * T;             // first query column of this lane
-        const bool cols_in_row = col0 < a.ldq;          // its 16 bytes lie inside the row
+        const bool cols_in_row = col0 < a.ldq;          // its T bytes lie inside the row
         int H[T], E[T];
 #pragma unroll
         for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
         int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
+        int pbest = 0, pt = -1, pj = 0;
         // Feeders: lane k holds the data of subject row 64*b + k: its residue
         // and H, F of the previous pass's last column (0 on the first pass).
         int fR, fH, fF, nR, nH, nF;
@@ -1274,7 +1337,7 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
             nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
             nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
         }
-        for (int t = 0; t < steps; ++t) {
+        auto step = [&](int t, auto fill) {
             if (t > 0 && (t & 63) == 0) {
                 fR = nR; fH = nH; fF = nF;
                 const int row = t + 64 + lane;
@@ -1289,38 +1352,15 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
             fH = shl1(fH, fH);
             fF = shl1(fF, fF);
             const int i = t - lane;             // this lane's subject row at this step
-            const bool real_row = i >= 0;       // rows before 0 keep the zero boundary
-            const bool track = real_row && i < n;
-            const int16_t *pr = prof + r * RS + lane * T;
-            int hdiag = hb_prev, hleft = hin, fprev = fin;
-            uint32_t cw[T / 4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int j = 0; j < T; ++j) {
-                const int hup = H[j];
-                const int e_ext = E[j] - alpha, e_open = hup - beta;
-                const int e = max(e_ext, e_open);
-                const int f_ext = fprev - alpha, f_open = hleft - beta;
-                const int fv = max(f_ext, f_open);
-                const int d = hdiag + (int)pr[j];
-                const int h = max(max(0, d), max(e, fv));
-                uint32_t code = h == 0 ? 4u : (h == d ? 0u : (h == e ? 1u : 2u));
-                code |= (e_open >= e_ext ? 8u : 0u) | (f_open >= f_ext ? 16u : 0u);
-                cw[j >> 2] |= code << (8 * (j & 3));
-                if (track && col0 + j < a.qlen && (h > best || (h == best && i < bi))) {
-                    best = h;
-                    bi = i;
-                    bj = col0 + j;
-                }
-                hdiag = hup;
-                H[j] = real_row ? h : 0;
-                E[j] = real_row ? e : 0;
-                hleft = H[j];
-                fprev = real_row ? fv : 0;
+            uint32_t cw[T / 4];
+            align_row<T, decltype(fill)::value>(a, H, E, prof + r * RS + lane * T, t, i, hb_prev,
+                                                hin, fin, pbest, pt, pj, cw, hout, fout);
+            if (i >= 0 && i < n && cols_in_row) {
+                uint8_t *dst = dir + (size_t)i * (size_t)a.ldq + col0;
+                if constexpr (T == 16) *(uint4 *)dst = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+                else if constexpr (T == 8) *(uint2 *)dst = make_uint2(cw[0], cw[1]);
+                else *(uint32_t *)dst = cw[0];
             }
-            hout = H[T - 1];
-            fout = fprev;
-            if (track && cols_in_row)
-                *(uint4 *)(dir + (size_t)i * (size_t)a.ldq + col0) = make_uint4(cw[0], cw[1], cw[2], cw[3]);
             hb_prev = hin;
             if (has_out) {
                 cH = shl1(hout, cH);
@@ -1330,6 +1370,18 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
                     wsc[2 * row] = cH;
                     wsc[2 * row + 1] = cF;
                 }
+            }
+        };
+        const int fill_end = steps < 63 ? steps : 63;
+        for (int t = 0; t < fill_end; ++t) step(t, std::true_type{});
+        for (int t = fill_end; t < steps; ++t) step(t, std::false_type{});
+        // merge the pass: a tie with an earlier pass keeps the smaller row
+        if (pt >= 0) {
+            const int pi = pt - lane;
+            if (pbest > best || (pbest == best && pi < bi)) {
+                best = pbest;
+                bi = pi;
+                bj = col0 + pj;
             }
         }
     }
@@ -1443,13 +1495,26 @@ __global__ void align_back_kernel(AlignArgs a) {
     out[5] = (int32_t)nrev;
 }
 
-int align_lds_bytes(int R) { return intra_lds_bytes(R, kAlignT); }
+// Columns per lane of the forward pass: the fewest passes, then the fewest
+// columns per lane (a short query leaves most of a wide pass idle while every
+// step still costs all of a lane's columns).
+int align_T_for(int qlen) {
+    if (qlen <= 256) return 4;
+    if (qlen <= 512) return 8;
+    return 16;
+}
 
 hipError_t launch_align(const AlignArgs &a, hipStream_t st) {
     if (a.n_pairs <= 0) return hipSuccess;
     const int grid = (a.n_pairs + kAlignWaves - 1) / kAlignWaves;
-    hipLaunchKernelGGL((align_fwd_kernel<kAlignWaves>), dim3(grid), dim3(kAlignWaves * 64),
-                       align_lds_bytes(a.R), st, a);
+    const int T = align_T_for(a.qlen);
+    const int lds = intra_lds_bytes(a.R, T);
+    if (T == 4)
+        hipLaunchKernelGGL((align_fwd_kernel<4, kAlignWaves>), dim3(grid), dim3(kAlignWaves * 64), lds, st, a);
+    else if (T == 8)
+        hipLaunchKernelGGL((align_fwd_kernel<8, kAlignWaves>), dim3(grid), dim3(kAlignWaves * 64), lds, st, a);
+    else
+        hipLaunchKernelGGL((align_fwd_kernel<16, kAlignWaves>), dim3(grid), dim3(kAlignWaves * 64), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(align_back_kernel, dim3((a.n_pairs + 63) / 64), dim3(64), 0, st, a);
@@ -1670,7 +1735,8 @@ hipError_t prepare_kernels() {
         (const void *)intra_kernel<8, 4>,  (const void *)intra_kernel<16, 4>,
         (const void *)intra2_kernel<4, 4>, (const void *)intra2_kernel<8, 4>,
         (const void *)intra2_kernel<16, 4>,
-        (const void *)align_fwd_kernel<kAlignWaves>,
+        (const void *)align_fwd_kernel<4, kAlignWaves>, (const void *)align_fwd_kernel<8, kAlignWaves>,
+        (const void *)align_fwd_kernel<16, kAlignWaves>,
     };
 #undef SWMI_FUSED
 #undef SWMI_K
