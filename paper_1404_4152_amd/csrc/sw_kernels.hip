@@ -1215,11 +1215,11 @@ hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStrea
 // bits 0-1 the source of H (0 diagonal, 1 E, 2 F), bit 2 H == 0, bit 3 E
 // opened, bit 4 F opened.  A lane hands H and F of its last column to the
 // lane on its right, which computes F of its first column (and that cell's
-// bit) itself.  A lane's 16 columns are 16 bytes of a row whose stride is
-// qlen rounded up to 16, so each step stores one aligned 16-byte vector.
-// Each lane keeps its first maximum (within a pass rows and columns come in
-// order; across passes a tie keeps the smaller row); the wave reduces by
-// (score desc, row asc, column asc).
+// bit) itself.  A lane's T columns (4, 8 or 16, by query length) are T bytes
+// of a row whose stride is qlen rounded up to 16, so each step stores one
+// aligned T-byte vector.  Each lane keeps its first strict maximum (within a
+// pass rows and columns come in order; across passes a tie keeps the smaller
+// row); the wave reduces by (score desc, row asc, column asc).
 // Traceback: one thread per pair walks back from the end cell, every read
 // bounds-checked.
 // ---------------------------------------------------------------------------
