@@ -138,6 +138,22 @@ struct AlignArgs {
     int32_t *out;            // per pair: score, q_begin, q_end, s_begin, s_end, n_ops
 };
 constexpr int kAlignWaves = 4;    // pairs per workgroup (they share the query profile)
+// Pipelined forward pass (one workgroup per pair, one wave per pass): most
+// passes (waves), rows of a pass boundary in the LDS ring, and the lag in
+// steps between consecutive passes.
+constexpr int kAlignPipeMax = 16;
+constexpr int kAlignPipeRing = 256;
+constexpr int kAlignPipeLag = 128;
+__host__ __device__ constexpr int align_pipe_prof_bytes(int R, int T, int P) {
+    return P * R * (64 * T + 16);   // int8 profiles of P passes
+}
+__host__ __device__ constexpr int align_pipe_lds_bytes(int R, int T, int P) {
+    return align_pipe_prof_bytes(R, T, P) + (P - 1) * kAlignPipeRing * 8 + 3 * P * 4;
+}
+// Columns per lane of the pipelined forward pass for this query (its pass
+// count in *P_out), or 0 when the query has one pass or its passes need more
+// waves or LDS than a workgroup has.
+int align_pipe_plan(int R, int qlen, int *P_out);
 hipError_t launch_align(const AlignArgs &a, hipStream_t st);
 
 // Top-k by (score desc, index asc) over rows of `n` scores, `nq` rows.

@@ -36,8 +36,9 @@
 //  * intra2_kernel: the same schedule in packed fp16, two subjects per wave;
 //    each lane reads its subject residues, and lane 0 its incoming H and F,
 //    from a per-wave LDS ring instead of shifted feeder registers.
-//  * align_fwd_kernel / align_back_kernel: alignment with traceback (the same
-//    schedule in int32 storing a direction byte per cell, then a walk back).
+//  * align_fwd_kernel / align_pipe_kernel / align_back_kernel: alignment with
+//    traceback (the same schedule in int32 storing a direction byte per cell,
+//    one wave per pair or one wave per pass of a pair, then a walk back).
 //  * topk_*: radix-select top-k of the score rows.
 //
 // Narrow-tier exactness.  A tier computes exactly while every intermediate
@@ -1229,34 +1230,52 @@ hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStrea
 // order, as (step, column); cells outside the subject or the query score 0 on
 // their diagonal and gap moves only lower a value, so none of them exceeds
 // the value of a real cell that precedes it.
-template <int T, bool FILL>
-__device__ __forceinline__ void align_row(const AlignArgs &a, int (&H)[T], int (&E)[T],
-                                          const int16_t *pr, int t, int i, int hdiag, int hleft,
-                                          int fprev, int &pbest, int &pt, int &pj, uint32_t (&cw)[T / 4],
-                                          int &hout, int &fout) {
-    static_assert(T % 4 == 0, "a lane stores whole 32-bit direction words");
-    // T int16 scores, read as T / 2 dwords; sign extension folds into the adds
-    uint32_t pw[T / 2];
-    if constexpr (T >= 8) {
+// The lane's T scores of one profile row, int16 or int8, read as whole
+// 4-, 8- or 16-byte LDS words.
+template <int T, typename S>
+__device__ __forceinline__ void load_scores(const S *pr, uint32_t (&pw)[T * sizeof(S) / 4]) {
+    constexpr int NW = T * (int)sizeof(S) / 4;
+    if constexpr (NW >= 4) {
 #pragma unroll
-        for (int k = 0; k < T / 8; ++k) {
+        for (int k = 0; k < NW / 4; ++k) {
             const uint4 v = ((const uint4 *)pr)[k];
             pw[4 * k] = v.x;
             pw[4 * k + 1] = v.y;
             pw[4 * k + 2] = v.z;
             pw[4 * k + 3] = v.w;
         }
-    } else {
+    } else if constexpr (NW == 2) {
         const uint2 v = *(const uint2 *)pr;
         pw[0] = v.x;
         pw[1] = v.y;
+    } else {
+        pw[0] = *(const uint32_t *)pr;
     }
+}
+
+template <int T, typename S>
+__device__ __forceinline__ int score_at(const uint32_t (&pw)[T * sizeof(S) / 4], int j) {
+    // sign extension folds into SDWA operands of the add that uses it
+    if constexpr (sizeof(S) == 2)
+        return (j & 1) ? ((int)pw[j >> 1] >> 16) : (int)(int16_t)(pw[j >> 1] & 0xffffu);
+    else
+        return (int)(int8_t)((pw[j >> 2] >> (8 * (j & 3))) & 0xffu);
+}
+
+template <int T, bool FILL, typename S>
+__device__ __forceinline__ void align_row(const AlignArgs &a, int (&H)[T], int (&E)[T],
+                                          const S *pr, int t, int i, int hdiag, int hleft,
+                                          int fprev, int &pbest, int &pt, int &pj, uint32_t (&cw)[T / 4],
+                                          int &hout, int &fout) {
+    static_assert(T % 4 == 0, "a lane stores whole 32-bit direction words");
+    uint32_t pw[T * sizeof(S) / 4];
+    load_scores<T, S>(pr, pw);
     const bool real_row = i >= 0;
 #pragma unroll
     for (int k = 0; k < T / 4; ++k) cw[k] = 0;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        const int sc = (j & 1) ? ((int)pw[j >> 1] >> 16) : (int)(int16_t)(pw[j >> 1] & 0xffffu);
+        const int sc = score_at<T, S>(pw, j);
         const int hup = H[j];
         const int e_ext = E[j] - a.alpha, e_open = hup - a.beta;
         const int e = max(e_ext, e_open);
@@ -1402,6 +1421,141 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
     }
 }
 
+// Pipelined forward pass: one workgroup per pair and one wave per pass of T
+// columns per lane, all passes at once, each with its int8 profile in LDS.  Wave w runs pass w
+// kAlignPipeLag steps behind wave w - 1: lane 63 of wave w - 1 writes H and F
+// of the pass's last column, row by row, to an LDS ring that wave w reads at
+// the start of each block of 64 steps.  Every wave meets a barrier after every
+// global block of 64 steps (the trip count is the same for all of them), so a
+// row written in one block is read in a later one, and a ring slot is read
+// before it is written again (the ring holds 256 rows, the lag is 128).
+template <int T>
+__global__ void __launch_bounds__(kAlignPipeMax * 64) align_pipe_kernel(AlignArgs a, int P) {
+    constexpr int PW = 64 * T;          // query columns per pass
+    constexpr int RS = PW + 16;         // int8 per profile row (padded)
+    constexpr int RING = kAlignPipeRing;
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // this wave's pass
+    const int pad = a.R - 1;
+    const int pair = blockIdx.x;
+    const int64_t id = a.ids[pair];
+    const int n = id >= 0 ? (int)(a.off[id + 1] - a.off[id]) : 0;
+    const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
+    uint8_t *dir = a.dir + (id >= 0 ? a.dir_off[pair] : 0);
+    int8_t *profs = (int8_t *)lds;
+    uint2 *rings = (uint2 *)(lds + align_pipe_prof_bytes(a.R, T, P) / 4);
+    int *red = (int *)(rings + (P - 1) * RING);
+
+    for (int e = threadIdx.x; e < P * a.R * PW; e += blockDim.x) {
+        const int pass = e / (a.R * PW), rc = e - pass * (a.R * PW);
+        const int r = rc / PW, c = rc - r * PW;
+        const int col = pass * PW + c;
+        profs[(pass * a.R + r) * RS + c] = col < a.qlen ? a.qp[(size_t)r * a.mpad + col] : (int8_t)0;
+    }
+    __syncthreads();
+
+    const int8_t *prof = profs + w * a.R * RS;
+    const bool has_in = w > 0, has_out = w + 1 < P;
+    const uint2 *in_ring = rings + (has_in ? w - 1 : 0) * RING;
+    uint2 *out_ring = rings + (has_out ? w : 0) * RING;
+    const int steps = n + 63;
+    const int nlb = n > 0 ? (steps + 63) / 64 : 0;          // blocks of this wave
+    constexpr int lagb = kAlignPipeLag / 64;
+    const int total = nlb > 0 ? nlb + (P - 1) * lagb : 0;   // same for every wave
+    const int col0 = w * PW + lane * T;
+    const bool cols_in_row = col0 < a.ldq;
+    int H[T], E[T];
+#pragma unroll
+    for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
+    int hb_prev = 0, hout = 0, fout = 0, r = pad;
+    int pbest = 0, pt = -1, pj = 0;
+    // residues of the next block, loaded one block ahead
+    int nR = lane < n ? s[lane] : pad;
+
+    for (int gb = 0; gb < total; ++gb) {
+        const int lb = gb - w * lagb;
+        if (lb >= 0 && lb < nlb) {
+            const int row = 64 * lb + lane;
+            int fR = nR;
+            nR = row + 64 < n ? s[row + 64] : pad;
+            int fH = 0, fF = 0;
+            if (has_in && row < n) {
+                const uint2 v = in_ring[row & (RING - 1)];
+                fH = (int)v.x;
+                fF = (int)v.y;
+            }
+            const int ue = steps - 64 * lb < 64 ? steps - 64 * lb : 64;
+            auto step = [&](int t, auto fill) {
+                r = shr1(fR, r);
+                const int hin = shr1(fH, hout);
+                const int fin = shr1(fF, fout);
+                fR = shl1(fR, fR);
+                fH = shl1(fH, fH);
+                fF = shl1(fF, fF);
+                const int i = t - lane;
+                uint32_t cw[T / 4];
+                align_row<T, decltype(fill)::value>(a, H, E, prof + r * RS + lane * T, t, i,
+                                                    hb_prev, hin, fin, pbest, pt, pj, cw, hout,
+                                                    fout);   // int8 scores
+                if (i >= 0 && i < n && cols_in_row) {
+                    uint8_t *dst = dir + (size_t)i * (size_t)a.ldq + col0;
+                    if constexpr (T == 16) *(uint4 *)dst = make_uint4(cw[0], cw[1], cw[2], cw[3]);
+                    else if constexpr (T == 8) *(uint2 *)dst = make_uint2(cw[0], cw[1]);
+                    else *(uint32_t *)dst = cw[0];
+                }
+                hb_prev = hin;
+                // lane 63 hands row t - 63 of the pass's last column on
+                if (has_out && lane == 63 && t >= 63)
+                    out_ring[(t - 63) & (RING - 1)] = make_uint2((uint32_t)hout, (uint32_t)fout);
+            };
+            for (int u = 0; u < ue; ++u) {
+                const int t = 64 * lb + u;
+                if (t < 63) step(t, std::true_type{});
+                else step(t, std::false_type{});
+            }
+        }
+        __syncthreads();
+    }
+    // this wave's candidate, then (score desc, row asc, column asc) over the
+    // wave and over the passes
+    int best = 0, bi = 0x7fffffff, bj = 0x7fffffff;
+    if (pt >= 0) {
+        best = pbest;
+        bi = pt - lane;
+        bj = col0 + pj;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const int ob = __shfl_xor(best, o, 64), oi = __shfl_xor(bi, o, 64), oj = __shfl_xor(bj, o, 64);
+        if (ob > best || (ob == best && (oi < bi || (oi == bi && oj < bj)))) {
+            best = ob;
+            bi = oi;
+            bj = oj;
+        }
+    }
+    if (lane == 0) {
+        red[3 * w] = best;
+        red[3 * w + 1] = bi;
+        red[3 * w + 2] = bj;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = red[0], ri = red[1], rj = red[2];
+        for (int k = 1; k < P; ++k) {
+            const int ob = red[3 * k], oi = red[3 * k + 1], oj = red[3 * k + 2];
+            if (ob > b || (ob == b && (oi < ri || (oi == ri && oj < rj)))) {
+                b = ob;
+                ri = oi;
+                rj = oj;
+            }
+        }
+        a.end[3 * pair] = b;
+        a.end[3 * pair + 1] = ri;
+        a.end[3 * pair + 2] = rj;
+    }
+}
+
 __global__ void align_back_kernel(AlignArgs a) {
     const int pair = blockIdx.x * blockDim.x + threadIdx.x;
     if (pair >= a.n_pairs) return;
@@ -1504,8 +1658,36 @@ int align_T_for(int qlen) {
     return 16;
 }
 
+// The pipelined forward pass takes the fewest columns per lane (4 or 8; at 16
+// the kernel would not fit 128 VGPRs) whose passes fit a workgroup (waves and
+// LDS); a query of one pass stays on the kernel that puts several pairs in a
+// workgroup.
+int align_pipe_plan(int R, int qlen, int *P_out) {
+    for (int T = 4; T <= 8; T *= 2) {
+        const int P = (qlen + 64 * T - 1) / (64 * T);
+        if (P < 2) return 0;
+        if (P <= kAlignPipeMax && align_pipe_lds_bytes(R, T, P) <= 160 * 1024 - 64) {
+            *P_out = P;
+            return T;
+        }
+    }
+    return 0;
+}
+
 hipError_t launch_align(const AlignArgs &a, hipStream_t st) {
     if (a.n_pairs <= 0) return hipSuccess;
+    int P = 0;
+    if (const int Tp = align_pipe_plan(a.R, a.qlen, &P)) {
+        const int lds = align_pipe_lds_bytes(a.R, Tp, P);
+        if (Tp == 4)
+            hipLaunchKernelGGL(align_pipe_kernel<4>, dim3(a.n_pairs), dim3(P * 64), lds, st, a, P);
+        else
+            hipLaunchKernelGGL(align_pipe_kernel<8>, dim3(a.n_pairs), dim3(P * 64), lds, st, a, P);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(align_back_kernel, dim3((a.n_pairs + 63) / 64), dim3(64), 0, st, a);
+        return hipGetLastError();
+    }
     const int grid = (a.n_pairs + kAlignWaves - 1) / kAlignWaves;
     const int T = align_T_for(a.qlen);
     const int lds = intra_lds_bytes(a.R, T);
@@ -1736,7 +1918,8 @@ hipError_t prepare_kernels() {
         (const void *)intra2_kernel<4, 4>, (const void *)intra2_kernel<8, 4>,
         (const void *)intra2_kernel<16, 4>,
         (const void *)align_fwd_kernel<4, kAlignWaves>, (const void *)align_fwd_kernel<8, kAlignWaves>,
-        (const void *)align_fwd_kernel<16, kAlignWaves>,
+        (const void *)align_fwd_kernel<16, kAlignWaves>, (const void *)align_pipe_kernel<4>,
+        (const void *)align_pipe_kernel<8>,
     };
 #undef SWMI_FUSED
 #undef SWMI_K
