@@ -370,7 +370,7 @@ def test_frame_model_needs_the_last_row_tail(orc):
 
 
 def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, G=4, init_out_shift=True,
-                       tail=True):
+                       tail=True, grp=4):
     """Frame fp16 arithmetic of the packed wave-per-pair kernel, replayed step
     by step: `lanes` lanes of T query columns each (a pass covers lanes * T
     columns), lane l computing subject row t - l at step t, H and F of its last
@@ -382,7 +382,10 @@ def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, G=4, init_o
     running best pairs (row, jj even) with (row - 1, jj + 1) into one register
     per even class, the last step's odd columns taken at the end (`tail`).
     Every carried value drops by rows * alpha at the end of each block of
-    `rows` steps.  Vectorised over pairs of equal shape (Q: (B, m), S: (B, n)).
+    `rows` steps.  As in the kernel, a pass with outputs runs one step past
+    its last block of `lanes` rows, and a pass without them rounds its steps
+    up to a whole group of `grp`; the extra steps see only pad rows.
+    Vectorised over pairs of equal shape (Q: (B, m), S: (B, n)).
     init_out_shift=False plants a wrong initial offset of the outputs handed
     on before step 0 (used by a negative control)."""
     assert G % 2 == 0 and T % G == 0
@@ -409,7 +412,7 @@ def model_intra2_frame(Q, S, M, alpha, beta, T=4, lanes=64, rows=32, G=4, init_o
     with np.errstate(over="ignore", invalid="ignore"):
         for p in range(npass):
             has_in, has_out = p > 0, p + 1 < npass
-            steps = nblk * lanes + lanes - 1 if has_out else n + lanes - 1
+            steps = nblk * lanes + lanes if has_out else (n + lanes - 1 + grp - 1) // grp * grp
             off0 = (-a * L).astype(np.int64)                          # (lanes,)
             H = np.stack([lanes_b(off0 + a * (cls[jj] - 1)) for jj in range(T)], axis=1)
             E = np.stack([lanes_b(off0 + a * cls[jj]) for jj in range(T)], axis=1)
@@ -537,16 +540,18 @@ def test_intra2_model_rejects_a_wrong_initial_offset(orc):
 
 def test_intra2_model_needs_the_last_step_tail(orc):
     """The running best takes a lane's odd columns of row r at row r + 1; the
-    last lane meets its last real row at the last step.  Queries planted at
-    the end of subjects (best cell in the last lane's last column, last row):
-    without the closing step the model must come out wrong."""
+    last lane meets its last real row at the last step unless the pass rounds
+    its steps up with pad rows.  Subjects of 49 rows (49 + 8 - 1 steps, a
+    whole number of groups, so no pad step) with queries planted at their
+    end (best cell in the last lane's last column, last row): without the
+    closing step the model must come out wrong."""
     rng = np.random.Generator(np.random.PCG64(19))
     A = 5
     M = np.full((A, A), -3, np.int8)
     np.fill_diagonal(M, 40)
     Q = rng.integers(0, A, size=(8, 32)).astype(np.uint8)       # 8 lanes x 4 columns: one pass
-    S = rng.integers(0, A, size=(8, 50)).astype(np.uint8)
-    S[:, 18:] = Q
+    S = rng.integers(0, A, size=(8, 49)).astype(np.uint8)
+    S[:, 17:] = Q
     check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8)
     with pytest.raises(AssertionError):
         check_intra2(orc, Q, S, M, 2, 12, 1848, T=4, lanes=8, tail=False)
