@@ -50,16 +50,27 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def code_digest(path):
+    """sha256 of a C++/HIP source with its // comments, trailing blanks and
+    empty lines removed: it changes when the code changes, not a comment."""
+    lines = []
+    for line in open(path, encoding="utf-8"):
+        code = line.split("//", 1)[0].rstrip()
+        if code.strip():
+            lines.append(code)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()
+
+
 def measured_traffic(workload, plan_overridden):
     """HBM bytes per launch of the lane-per-subject kernel from the committed
     FETCH_SIZE / WRITE_SIZE counter passes, if they were taken on this exact
-    kernel source and workload; None otherwise."""
+    kernel code and workload; None otherwise."""
     rec_path = os.path.join(ROOT, "profiles", f"inter_kernel_{workload}_traffic.json")
     src = os.path.join(ROOT, "paper_1404_4152_amd", "csrc", "sw_kernels.hip")
     if plan_overridden or not os.path.exists(rec_path):
         return None
     rec = json.load(open(rec_path))
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get("kernel_source_sha256"):
+    if code_digest(src) != rec.get("kernel_code_sha256"):
         return None
     return rec["traffic_bytes_per_launch"]
 

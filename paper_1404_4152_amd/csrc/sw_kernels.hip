@@ -1422,10 +1422,10 @@ __global__ void __launch_bounds__(W * 64) align_fwd_kernel(AlignArgs a) {
 }
 
 // Pipelined forward pass: one workgroup per pair and one wave per pass of T
-// columns per lane, all passes at once, each with its int8 profile in LDS.  Wave w runs pass w
-// kAlignPipeLag steps behind wave w - 1: lane 63 of wave w - 1 writes H and F
-// of the pass's last column, row by row, to an LDS ring that wave w reads at
-// the start of each block of 64 steps.  Every wave meets a barrier after every
+// columns per lane, all passes at once, each with its int8 profile in LDS.
+// Wave w runs pass w kAlignPipeLag steps behind wave w - 1: lane 63 of wave
+// w - 1 writes H and F of the pass's last column, row by row, to an LDS ring
+// that wave w reads at the start of each block of 64 steps.  Every wave meets a barrier after every
 // global block of 64 steps (the trip count is the same for all of them), so a
 // row written in one block is read in a later one, and a ring slot is read
 // before it is written again (the ring holds 256 rows, the lag is 128).
