@@ -260,6 +260,29 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
         db.close()
 
 
+@pytest.mark.parametrize("A", [3, 32])
+def test_packed_wave_per_pair_alphabets(swmi, orc, A):
+    """The packed kernel's LDS holds the profile (R = A + 1 rows) and, after
+    it, one feed ring per wave: the smallest alphabets and the largest
+    (SW_MAX_ALPHABET, two workgroups per CU) with queries of one to three
+    passes, ragged subject lengths and empty subjects."""
+    rng = np.random.Generator(np.random.PCG64(700 + A))
+    M = sd.random_matrix(rng, A)
+    res, off = random_db(rng, 9000, A, 0, 200, zero_every=89)
+    db = swmi.Database(res, off, A, long_threshold=1)
+    try:
+        db.set_opts(tier=1)
+        for L in [7, 700, 2100]:
+            q = sd.uniform_residues(rng, L, A)
+            print(f"packed wave-per-pair A={A} qlen={L}", flush=True)
+            exp = orc.search(q, res, off, M, 2, 12)
+            expect_equal(db.search(q, M, 2, 12), exp, f"packed A={A} L={L}")
+            st = db.stats()
+            assert st["intra_pairs"] == 9000 and st["inter_cells"] == 0
+    finally:
+        db.close()
+
+
 def test_planted_homologs_exceed_narrow_tiers(swmi, orc):
     """Scores above 1920 (fp16 tier) and above 32767 (int16 tier) stay exact."""
     rng = np.random.Generator(np.random.PCG64(5))
