@@ -239,7 +239,7 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     """The packed fp16 wave-per-pair kernel (every subject on the long list,
     9,000 pairs) with queries of one, two and three passes of 64 x T columns:
     the pass boundary is stored as true values and re-offset on the way in.
-    Subjects span several 64-row feeder blocks and 32-step frame periods;
+    Subjects span several 64-row feed blocks and 32-step frame periods;
     alpha 29 flags every half (ceiling 0) and the recompute keeps it exact."""
     rng = np.random.Generator(np.random.PCG64(400 + alpha))
     M = sd.blosum_style_matrix()
