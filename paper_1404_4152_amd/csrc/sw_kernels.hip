@@ -1084,8 +1084,10 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     best_io = __builtin_elementwise_maximum(B[0] - oe2, B[1] - (oe2 + ops.k(2)));
 }
 
+// At T = 16 the protein-sized profile already holds a CU to three of these
+// workgroups, so the kernel may use the registers of three waves per SIMD.
 template <int T, int W>
-__global__ void __launch_bounds__(W * 64, 4) intra2_kernel(IntraArgs a) {
+__global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraArgs a) {
     typedef Lane<TIER_F16X2> L;
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // fp16 entries per profile row (padded)
