@@ -1882,10 +1882,56 @@ __global__ void topk_final(const int32_t *state, const int32_t *eqcnt, int nblk,
     }
 }
 
+// Top-k of a short score row in one workgroup per query: a bitonic sort of
+// 64-bit keys (2^31 - 1 - score, index) in LDS, ascending, so the first k are
+// the scores in descending order with equal scores by ascending index.  The
+// radix select above takes eleven launches, which cost more than the sort at
+// this size.
+constexpr int kTopkSmallN = 4096;
+
+__global__ void __launch_bounds__(1024) topk_small(const int32_t *scores, int64_t n,
+                                                   const int32_t *rows, int32_t k,
+                                                   int32_t *top_s, int64_t *top_i) {
+    __shared__ uint64_t key[kTopkSmallN];
+    const int q = blockIdx.x;
+    const int32_t *row = scores + (size_t)(rows ? rows[q] : q) * n;
+    int N = 1;
+    while (N < n) N <<= 1;
+    for (int x = threadIdx.x; x < N; x += blockDim.x)
+        key[x] = x < n ? ((uint64_t)(uint32_t)(0x7fffffff - row[x]) << 32) | (uint32_t)x
+                       : ~(uint64_t)0;
+    __syncthreads();
+    for (int size = 2; size <= N; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int x = threadIdx.x; x < N; x += blockDim.x) {
+                const int y = x ^ stride;
+                if (y > x) {
+                    const bool up = (x & size) == 0;
+                    const uint64_t a = key[x], b = key[y];
+                    if ((a > b) == up) {
+                        key[x] = b;
+                        key[y] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    for (int x = threadIdx.x; x < k; x += blockDim.x) {
+        const bool real = x < n;
+        const uint64_t v = real ? key[x] : 0;
+        top_s[(size_t)q * k + x] = real ? 0x7fffffff - (int32_t)(v >> 32) : -1;
+        top_i[(size_t)q * k + x] = real ? (int64_t)(uint32_t)v : -1;
+    }
+}
+
 hipError_t launch_topk(const int32_t *scores, int64_t n, int32_t nq, const int32_t *rows,
                        int32_t k, const TopkWork &w, int32_t *top_s, int64_t *top_i,
                        hipStream_t st) {
     if (nq <= 0) return hipSuccess;
+    if (n <= kTopkSmallN) {
+        hipLaunchKernelGGL(topk_small, dim3(nq), dim3(1024), 0, st, scores, n, rows, k, top_s, top_i);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(topk_init, dim3(nq), dim3(256), 0, st, w.state, w.hist, k);
     int64_t hb = (n + 2047) / 2048;
     if (hb < 1) hb = 1;
