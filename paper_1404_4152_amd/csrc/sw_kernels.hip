@@ -39,7 +39,8 @@
 //  * align_fwd_kernel / align_pipe_kernel / align_back_kernel: alignment with
 //    traceback (the same schedule in int32 storing a direction byte per cell,
 //    one wave per pair or one wave per pass of a pair, then a walk back).
-//  * topk_*: radix-select top-k of the score rows.
+//  * topk_*: radix-select top-k of the score rows (one-workgroup bitonic sort
+//    for rows of at most 4,096 subjects).
 //
 // Narrow-tier exactness.  A tier computes exactly while every intermediate
 // value is representable; it flags a lane whose best reaches the tier's
