@@ -470,12 +470,13 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
     L.grid_inter = (int)std::min<int64_t>(
         L.fused_long ? n_inter + n_intra : n_inter,
         inter_max_grid(db->R, plan.tier, plan.strip, plan.waves, L.fused_long ? L.Ti : 0));
-    const int per_cu = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, L.Ti) + 64), 8));
+    const int per_cu =
+        std::max(1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, L.Ti, kIntraWaves) + 64), 8));
     L.grid_long = (int)std::min<int64_t>(n_intra, (int64_t)per_cu * db->cus);
     const int per_cu2 = std::max(
-        1, std::min(160 * 1024 / (intra2_lds_bytes(db->R, L.Ti, kIntraWaves) + 64), 8));
+        1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, L.Ti, kIntraWaves) + 64), 8));
     L.grid_packed = (int)std::min<int64_t>(n_intra, (int64_t)per_cu2 * db->cus);
-    const int per_cu16 = std::max(1, std::min(160 * 1024 / (intra_lds_bytes(db->R, 16) + 64), 8));
+    const int per_cu16 = std::max(1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, 16, 1) + 64), 8));
     L.grid_ovf = std::min(per_cu16 * db->cus * kIntraWaves, 4096);
     return L;
 }
@@ -483,7 +484,7 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
 bool fuse_ok(const sw_db *db, const Plan &plan, int ti) {
     return plan.tier == TIER_F16X2 && plan.strip == kFuseStrip &&
            (plan.waves == 4 || plan.waves == 6 || plan.waves == 8) &&
-           intra_lds_bytes(db->R, ti) <= inter_lds_bytes(db->R, plan.strip);
+           wpp_lds_bytes(db->R, ti, plan.waves) <= inter_lds_bytes(db->R, plan.strip);
 }
 
 int64_t intra_scratch_rows(const sw_db *db) {

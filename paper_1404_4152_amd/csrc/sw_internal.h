@@ -105,14 +105,14 @@ hipError_t prepare_kernels();
 constexpr int kFuseStrip = 32;
 hipError_t launch_inter(const InterArgs &a, const IntraArgs *la, int ti, int tier, int strip,
                         int waves, int grid, hipStream_t st);
-int inter_lds_bytes(int R, int strip, int ti = 0);
+int inter_lds_bytes(int R, int strip, int ti = 0, int waves = 4);
 // resident workgroups that fit (ti as for launch_inter)
 int inter_max_grid(int R, int tier, int strip, int waves, int ti = 0);
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);
-// LDS of the packed wave-per-pair kernel: the profile and one feed ring per wave.
-int intra2_lds_bytes(int R, int T, int waves);
+// LDS of a wave-per-pair workgroup: the profile and one feed ring per wave.
+int wpp_lds_bytes(int R, int T, int waves);
 // Packed-fp16 wave-per-pair kernel: each wave aligns one query with two
 // subjects (item_ids holds 2 * waves ids per item).
 hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);

@@ -31,11 +31,11 @@
 //    (the intra-sequence model of section III.C, laid out as a systolic
 //    array along anti-diagonals rather than striped).  Lane l owns T query
 //    columns; at step t it computes subject row t - l; H and F of its last
-//    column move to lane l+1 with a DPP wave shift.  Serves long subjects,
-//    small databases and the exact recompute of flagged narrow-tier lanes.
-//  * intra2_kernel: the same schedule in packed fp16, two subjects per wave;
-//    each lane reads its subject residues, and lane 0 its incoming H and F,
-//    from a per-wave LDS ring instead of shifted feeder registers.
+//    column move to lane l+1 with a DPP wave shift.  Each lane reads its
+//    subject residue, and lane 0 its incoming H and F, from a per-wave LDS
+//    ring.  Serves long subjects, small databases and the exact recompute of
+//    flagged narrow-tier lanes.
+//  * intra2_kernel: the same schedule in packed fp16, two subjects per wave.
 //  * align_fwd_kernel / align_pipe_kernel / align_back_kernel: alignment with
 //    traceback (the same schedule in int32 storing a direction byte per cell,
 //    one wave per pair or one wave per pass of a pair, then a walk back).
@@ -593,9 +593,9 @@ __global__ void __launch_bounds__(W * 64, (InterOcc<T, TIER>::value))
     }
 }
 
-int inter_lds_bytes(int R, int strip, int ti) {
+int inter_lds_bytes(int R, int strip, int ti, int waves) {
     const int lane = (R * R * (strip + 4) + R * (strip / 2)) * 4;
-    return ti > 0 ? std::max(lane, intra_lds_bytes(R, ti)) : lane;
+    return ti > 0 ? std::max(lane, wpp_lds_bytes(R, ti, waves)) : lane;
 }
 
 static int lds_per_cu() { return 160 * 1024; }
@@ -604,7 +604,7 @@ template <int T, int W, int TIER, int TI>
 static int inter_resident_t(int R) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inter_kernel<T, W, TIER, TI>, W * 64,
-                                                     inter_lds_bytes(R, T, TI)) != hipSuccess)
+                                                     inter_lds_bytes(R, T, TI, W)) != hipSuccess)
         per_cu = 0;
     return per_cu;
 }
@@ -638,7 +638,7 @@ int inter_max_grid(int R, int tier, int strip, int waves, int ti) {
 #undef SWMI_RES_CASE
     if (per_cu < 1) {
         // runtime query unavailable: bound by LDS and 8 waves per SIMD
-        const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip, ti) + 64);
+        const int by_lds = lds_per_cu() / (inter_lds_bytes(R, strip, ti, waves) + 64);
         const int by_waves = 32 / waves;
         per_cu = by_lds < by_waves ? by_lds : by_waves;
         if (per_cu < 1) per_cu = 1;
@@ -649,7 +649,7 @@ int inter_max_grid(int R, int tier, int strip, int waves, int ti) {
 template <int T, int W, int TIER, int TI>
 static hipError_t launch_inter_t(const InterArgs &a, const IntraArgs &la, int grid, hipStream_t st) {
     int magic = (65536 + a.R - 1) / a.R;
-    const int lds = inter_lds_bytes(a.R, T, TI);
+    const int lds = inter_lds_bytes(a.R, T, TI, W);
     hipLaunchKernelGGL((inter_kernel<T, W, TIER, TI>), dim3(grid), dim3(W * 64), lds, st, a, la,
                        magic);
     return hipGetLastError();
@@ -697,6 +697,18 @@ __device__ __forceinline__ int shr1(int old, int src) {
 __device__ __forceinline__ int shl1(int old, int src) {
     return __builtin_amdgcn_update_dpp(old, src, 0x130, 0xf, 0xf, false);
 }
+
+// Per-wave LDS ring of the wave-per-pair kernels, 638 words after the
+// profile.  Entry x (0 <= x < 128) of the residue-code arrays A and B covers
+// row 64(b - 1) + x during block b of 64 steps; the lane-0 feeds H and F keep
+// only the current block (entries 64..127); the output arrays OH and OF take
+// entries 1..127.  Reads of entries that an array does not keep land, in
+// bounds, on another array and only feed lanes whose value is discarded.
+// (The int32 kernel, one subject per wave, leaves B unused.)
+constexpr int kRingA = 0, kRingB = 128, kRingH = 192, kRingF = 256, kRingOH = 383, kRingOF = 510;
+constexpr int kRing2Bytes = 638 * 4;
+
+int wpp_lds_bytes(int R, int T, int waves) { return intra_lds_bytes(R, T) + waves * kRing2Bytes; }
 
 template <int T>
 __device__ __forceinline__ void intra_row(int (&H)[T], int (&E)[T], const uint2 *pr, int hb_prev,
@@ -750,6 +762,7 @@ __device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t 
     int16_t *prof = (int16_t *)lds;
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
+    uint32_t *ring = lds + (a.R * RS * 2 + w * kRing2Bytes) / 4;   // after the profile
     const int pad = a.R - 1;
     const int q = a.item_q[it];
     const int id = a.item_ids[(size_t)it * W + w];
@@ -774,48 +787,72 @@ __device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t 
 
         const bool has_in = p > 0, has_out = p + 1 < npass;
         const int nblk = (n + 63) / 64;
-        const int steps = has_out ? nblk * 64 + 63 : n + 63;
+        // with outputs, the last block's read-back needs step 64 * nblk + 63
+        const int steps = has_out ? nblk * 64 + 64 : n + 63;
         int H[T], E[T];
 #pragma unroll
         for (int j = 0; j < T; ++j) { H[j] = 0; E[j] = 0; }
-        int hb_prev = 0, hout = 0, fout = 0, r = pad, cH = 0, cF = 0;
-        // Feeders: lane k holds the data of subject row 64*b + k; lane 0's
-        // value is consumed each step, then the feeder shifts down a lane.
-        int fR, fH, fF, nR, nH, nF;
-        {
-            const int row = lane;
-            fR = row < n ? s[row] : pad;
-            fH = (has_in && row < n) ? wsc[2 * row] : 0;
-            fF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
-            const int row2 = 64 + lane;
-            nR = row2 < n ? s[row2] : pad;
-            nH = (has_in && row2 < n) ? wsc[2 * row2] : 0;
-            nF = (has_in && row2 < n) ? wsc[2 * row2 + 1] : 0;
-        }
-        for (int t = 0; t < steps; ++t) {
-            if (t > 0 && (t & 63) == 0) {
-                fR = nR; fH = nH; fF = nF;
-                const int row = t + 64 + lane;
-                nR = row < n ? s[row] : pad;
-                nH = (has_in && row < n) ? wsc[2 * row] : 0;
-                nF = (has_in && row < n) ? wsc[2 * row + 1] : 0;
+        int hb_prev = 0, hout = 0, fout = 0;
+        // Lane l fills entry 64 + l of the ring's A, H and F with row 64b + l
+        // of block b (A: residue code, H and F: the previous pass's last
+        // column, 0 on the first pass).  At step 64b + u lane l reads entry
+        // 64 + u - l; every lane writes its outputs to that entry of OH and
+        // OF, and entry u + 1 ends the block holding lane 63's.
+        auto feed = [&](int row, uint32_t &fa, uint32_t &fh, uint32_t &ff) {
+            fa = row < n ? s[row] : pad;
+            fh = (has_in && row < n) ? (uint32_t)wsc[2 * row] : 0u;
+            ff = (has_in && row < n) ? (uint32_t)wsc[2 * row + 1] : 0u;
+        };
+        uint32_t cA, cHf, cFf, nA, nH, nF;
+        feed(lane, cA, cHf, cFf);   // only until they are in the ring
+        feed(64 + lane, nA, nH, nF);
+        ring[kRingA + lane] = pad;
+        ring[kRingA + 64 + lane] = cA;
+        ring[kRingH + 64 + lane] = cHf;
+        ring[kRingF + 64 + lane] = cFf;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        uint32_t *rl = ring + 64 - lane;
+        for (int tb = 0; tb < steps; tb += 64) {
+            if (tb > 0) {
+                // block tb/64 - 1 moves down, block tb/64 comes in
+                ring[kRingA + lane] = cA;
+                ring[kRingA + 64 + lane] = nA;
+                ring[kRingH + 64 + lane] = nH;
+                ring[kRingF + 64 + lane] = nF;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                cA = nA;
+                feed(tb + 64 + lane, nA, nH, nF);
             }
-            r = shr1(fR, r);
-            const int hin = shr1(fH, hout);
-            const int fin = shr1(fF, fout);
-            fR = shl1(fR, fR);
-            fH = shl1(fH, fH);
-            fF = shl1(fF, fF);
-            const uint2 *pr = (const uint2 *)(prof + r * RS + lane * T);
-            intra_row<T>(H, E, pr, hb_prev, fin, alpha, beta, best, hout, fout);
-            hb_prev = hin;
+            const int ue = __builtin_amdgcn_readfirstlane(steps - tb < 64 ? steps - tb : 64);
+            for (int u = 0; u < ue; ++u) {
+                uint32_t *e = rl + u;
+                const int hin = shr1((int)e[kRingH], hout);
+                const int fin = shr1((int)e[kRingF], fout);
+                // residue codes are below 2^24, so the 24-bit multiply is exact
+                const uint2 *pr = (const uint2 *)(prof + (__umul24(e[kRingA], RS) + lane * T));
+                intra_row<T>(H, E, pr, hb_prev, fin, alpha, beta, best, hout, fout);
+                hb_prev = hin;
+                if (has_out) {
+                    e[kRingOH] = (uint32_t)hout;
+                    e[kRingOF] = (uint32_t)fout;
+                }
+            }
             if (has_out) {
-                cH = shl1(hout, cH);
-                cF = shl1(fout, cF);
-                if ((t & 63) == 62 && t >= 126) {
-                    const int row = t - 126 + lane;
-                    wsc[2 * row] = cH;
-                    wsc[2 * row + 1] = cF;
+                // the block's last step t = tb + 63 has passed; entries 1..64
+                // hold lane 63's rows t - 126 .. t - 63 (steps with outputs run
+                // whole blocks)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int row = tb + 63 - 126 + lane;
+                const uint32_t oh = ring[kRingOH + 1 + lane], of = ring[kRingOF + 1 + lane];
+                if (row >= 0 && row < n) {
+                    wsc[2 * row] = (int)oh;
+                    wsc[2 * row + 1] = (int)of;
                 }
             }
         }
@@ -914,16 +951,6 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
     fout = f;
 }
 
-// Per-wave LDS ring of the packed kernel, 638 words.  Entry x (0 <= x < 128)
-// of the residue-code arrays A and B covers row 64(b - 1) + x during block b
-// of 64 steps; the lane-0 feeds H and F keep only the current block (entries
-// 64..127); the output arrays OH and OF take entries 1..127.  Reads of
-// entries that an array does not keep land, in bounds, on another array and
-// only feed lanes whose value is discarded.
-constexpr int kRingA = 0, kRingB = 128, kRingH = 192, kRingF = 256, kRingOH = 383, kRingOF = 510;
-constexpr int kRing2Bytes = 638 * 4;
-
-int intra2_lds_bytes(int R, int T, int waves) { return intra_lds_bytes(R, T) + waves * kRing2Bytes; }
 
 template <int T, bool HAS_IN, bool HAS_OUT>
 __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame &ops,
@@ -1170,7 +1197,7 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
 
 template <int T, int W>
 static hipError_t launch_intra2_t(const IntraArgs &a, int grid, hipStream_t st) {
-    const int lds = intra2_lds_bytes(a.R, T, W);
+    const int lds = wpp_lds_bytes(a.R, T, W);
     hipLaunchKernelGGL((intra2_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
     return hipGetLastError();
 }
@@ -1185,7 +1212,7 @@ hipError_t launch_intra2(const IntraArgs &a, int T, int waves, int grid, hipStre
 
 template <int T, int W>
 static hipError_t launch_intra_t(const IntraArgs &a, int grid, hipStream_t st) {
-    const int lds = intra_lds_bytes(a.R, T);
+    const int lds = wpp_lds_bytes(a.R, T, W);
     hipLaunchKernelGGL((intra_kernel<T, W>), dim3(grid), dim3(W * 64), lds, st, a);
     return hipGetLastError();
 }
