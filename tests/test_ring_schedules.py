@@ -1,8 +1,9 @@
 """Host-side replay of the LDS rings' index and timing arithmetic in the
 wave-per-pair kernels, with the constants read from the kernel sources:
 
-- the packed kernel's per-wave ring (residue codes, lane-0 feeds and the
-  last-lane outputs share 638 words through overlapping arrays);
+- the wave-per-pair kernels' per-wave ring (residue codes, lane-0 feeds and
+  the last-lane outputs share 638 words through overlapping arrays; the int32
+  kernel leaves the second residue array unused);
 - the pipelined traceback kernel's pass-boundary ring (one wave per pass,
   a fixed lag between passes, a barrier after every 64-step block).
 
@@ -39,7 +40,7 @@ def _ring_words():
     return int(m.group(1))
 
 
-def test_packed_ring_reads_stay_in_bounds_and_hit_kept_entries():
+def test_ring_reads_stay_in_bounds_and_hit_kept_entries():
     """At step 64b + u lane l reads entry e = 64 + u - l of every array (all
     lanes, 0 <= u, l < 64).  The word stays inside the ring; lane 0's H and F
     entries and every lane's residue entries are ones the array keeps (A, B:
@@ -59,7 +60,7 @@ def test_packed_ring_reads_stay_in_bounds_and_hit_kept_entries():
                     assert name in ("kRingH", "kRingF") and l > 0
 
 
-def test_packed_ring_arrays_do_not_overlap_where_kept_or_written():
+def test_ring_arrays_do_not_overlap_where_kept_or_written():
     """Kept entries of the input arrays and written entries of the output
     arrays (1..127, every lane writes) never share a word."""
     words = _ring_words()
@@ -74,7 +75,7 @@ def test_packed_ring_arrays_do_not_overlap_where_kept_or_written():
             owned[w] = name
 
 
-def test_packed_ring_output_entry_is_lane_63s_at_block_end():
+def test_ring_output_entry_is_lane_63s_at_block_end():
     """Every lane writes its outputs of step t to entry 64 + (t mod 64) - l.
     At the end of a 64-step block, entries 1..64 must hold lane 63's values of
     that block, in row order (entry p: the row lane 63 produced at step p - 1
