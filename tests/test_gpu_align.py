@@ -32,14 +32,15 @@ def check_all(orc, got, q, res, off, ids, M, alpha, beta, what):
         assert g == exp, f"{what}: id {i} (pair {k}): got {g}, expected {exp}"
 
 
-@pytest.mark.parametrize("qlen", [1, 37, 1024, 1025, 2500, 4100, 6200])
+@pytest.mark.parametrize("qlen", [1, 37, 1024, 1025, 2500, 4000, 4100, 6100, 6200])
 def test_random_db_align(swmi, orc, qlen):
     """Subjects of 0..1,500 residues (some empty), a query copy planted in
     some.  The query lengths reach every forward kernel: one wave per pair
     for a single pass (1, 37) and for passes that do not fit a workgroup
     (6,200: seven passes of 1,024 columns, one after another); one wave per
-    pass, pipelined, at 4 columns per lane (1,024 to 2,500: 4 to 10 passes)
-    and at 8 (4,100: 9 passes)."""
+    pass, pipelined, at 4 columns per lane (1,024 to 4,000: 4 to 16 passes,
+    16 being the most waves a workgroup takes) and at 8 (4,100 and 6,100: 9
+    and 12 passes, 12 filling the LDS)."""
     rng = np.random.Generator(np.random.PCG64(500 + qlen))
     A = 20
     M = sd.blosum_style_matrix()
