@@ -1144,7 +1144,12 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
         const uint8_t *sa = id_a >= 0 ? a.res + a.off[id_a] : a.res;
         const uint8_t *sb = id_b >= 0 ? a.res + a.off[id_b] : a.res;
         const int mp = a.qs.mpad[q];
-        const int npass = (a.qs.qlen[q] + PW - 1) / PW;
+        const int qlen = a.qs.qlen[q];
+        const int npass = (qlen + PW - 1) / PW;
+        // The last pass takes the fewest columns per lane that hold its
+        // columns: every step costs all of a lane's columns, used or not.
+        const int rem = qlen - (npass - 1) * PW;
+        const int tl = T == 16 ? (rem <= 256 ? 4 : rem <= 512 ? 8 : 16) : T;
         const int8_t *qp = a.qs.qp[q];
         const int alpha = a.qs.gap[2 * q];
         const LaneFrame ops(min(alpha, kFrameMaxAlpha), a.qs.gap[2 * q + 1]);
@@ -1152,16 +1157,30 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
         h2 best = L::zero();
 
         for (int p = 0; p < npass; ++p) {
+            const bool last = p + 1 == npass;
+            const int pw = 64 * (last ? tl : T), rs = pw + 8;   // this pass's width and row stride
             __syncthreads();
-            for (int e = threadIdx.x; e < a.R * PW; e += W * 64) {
-                const int r = e / PW, c = e - r * PW;
+            for (int e = threadIdx.x; e < a.R * pw; e += W * 64) {
+                const int r = e / pw, c = e - r * pw;
                 const int col = p * PW + c;
                 const int bias = col % kFrameCols == 0 ? ops.bias0 : ops.bias1;
-                prof[r * RS + c] = L::enc((col < mp ? (int)qp[(size_t)r * mp + col] : 0) + bias);
+                prof[r * rs + c] = L::enc((col < mp ? (int)qp[(size_t)r * mp + col] : 0) + bias);
             }
             __syncthreads();
             if (n <= 0) continue;
-            const bool has_in = p > 0, has_out = p + 1 < npass;
+            const bool has_in = p > 0, has_out = !last;
+            if constexpr (T == 16) {
+                if (last && tl == 4) {
+                    if (has_in) intra2_pass<4, true, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    else intra2_pass<4, false, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    continue;
+                }
+                if (last && tl == 8) {
+                    if (has_in) intra2_pass<8, true, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    else intra2_pass<8, false, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    continue;
+                }
+            }
             if (has_in) {
                 if (has_out) intra2_pass<T, true, true>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
                 else intra2_pass<T, true, false>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);

@@ -239,6 +239,7 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     """The packed fp16 wave-per-pair kernel (every subject on the long list,
     9,000 pairs) with queries of one, two and three passes of 64 x T columns:
     the pass boundary is stored as true values and re-offset on the way in.
+    The last pass narrows to 4 columns per lane (1,100, 2,100) or 8 (1,400).
     Subjects span several 64-row feed blocks and 32-step frame periods;
     alpha 29 flags every half (ceiling 0) and the recompute keeps it exact."""
     rng = np.random.Generator(np.random.PCG64(400 + alpha))
@@ -247,7 +248,7 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     db = swmi.Database(res, off, 20, long_threshold=1)
     try:
         db.set_opts(tier=1)
-        for L in [5, 300, 1100, 2100]:
+        for L in [5, 300, 1100, 1400, 2100]:
             q = sd.random_residues(rng, L)
             print(f"packed wave-per-pair alpha={alpha} qlen={L}", flush=True)
             exp = orc.search(q, res, off, M, alpha, beta)
