@@ -261,6 +261,27 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
         db.close()
 
 
+def test_packed_wave_per_pair_batch_mixed_lengths(swmi, orc):
+    """A batch whose longest query sets 16 columns per lane for the packed
+    kernel: shorter queries run their single (or last) pass at 4 or 8
+    columns per lane, longer ones a narrowed last pass after full ones."""
+    rng = np.random.Generator(np.random.PCG64(812))
+    M = sd.blosum_style_matrix()
+    res, off = random_db(rng, 9000, 20, 0, 180, zero_every=83)
+    qs = [sd.random_residues(rng, L) for L in (40, 300, 700, 1100, 1400)]
+    db = swmi.Database(res, off, 20, long_threshold=1)
+    try:
+        db.set_opts(tier=1)
+        print("packed batch of mixed lengths", flush=True)
+        ts, ti, al = db.search_batch(qs, M, 2, 12, 10, all_scores=True)
+        st = db.stats()
+        assert st["intra_pairs"] == 9000 * len(qs) and st["inter_cells"] == 0
+        for x, q in enumerate(qs):
+            expect_equal(al[x], orc.search(q, res, off, M, 2, 12), f"packed batch q{x}")
+    finally:
+        db.close()
+
+
 @pytest.mark.parametrize("A", [3, 32])
 def test_packed_wave_per_pair_alphabets(swmi, orc, A):
     """The packed kernel's LDS holds the profile (R = A + 1 rows) and, after
