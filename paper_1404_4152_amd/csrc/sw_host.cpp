@@ -192,9 +192,7 @@ struct Launch {
     Plan plan;
     int Ti = 16;
     int grid_inter = 0, grid_long = 0, grid_ovf = 0;
-    int grid_packed = 0;        // grid of the packed kernel, used when packed_long
     bool packed_long = false;   // wave-per-pair items hold two subjects per wave
-    int long_grid() const { return packed_long ? grid_packed : grid_long; }
     bool fused_long = false;    // wave-per-pair items run in the lane-per-subject kernel
 };
 
@@ -470,12 +468,11 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
     L.grid_inter = (int)std::min<int64_t>(
         L.fused_long ? n_inter + n_intra : n_inter,
         inter_max_grid(db->R, plan.tier, plan.strip, plan.waves, L.fused_long ? L.Ti : 0));
+    // either wave-per-pair kernel (int32 or packed: the same profile and feed
+    // rings per workgroup)
     const int per_cu =
         std::max(1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, L.Ti, kIntraWaves) + 64), 8));
     L.grid_long = (int)std::min<int64_t>(n_intra, (int64_t)per_cu * db->cus);
-    const int per_cu2 = std::max(
-        1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, L.Ti, kIntraWaves) + 64), 8));
-    L.grid_packed = (int)std::min<int64_t>(n_intra, (int64_t)per_cu2 * db->cus);
     const int per_cu16 = std::max(1, std::min(160 * 1024 / (wpp_lds_bytes(db->R, 16, 1) + 64), 8));
     L.grid_ovf = std::min(per_cu16 * db->cus * kIntraWaves, 4096);
     return L;
@@ -544,7 +541,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         la.item_ids = b.il_ids;
         la.n_items = (int32_t)b.n_intra;
         la.counter = b.counters + 2;
-        if (L.packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_packed, db->aux));
+        if (L.packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_long, db->aux));
         else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, db->aux));
         HIPX(hipEventRecord(db->join, db->aux));
         return SW_OK;
@@ -588,7 +585,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         la.item_ids = b.il_ids;
         la.n_items = (int32_t)b.n_intra;
         la.counter = b.counters + 2;
-        if (packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_packed, st));
+        if (packed_long) HIPX(launch_intra2(la, L.Ti, kIntraWaves, L.grid_long, st));
         else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
     }
     if (fork) HIPX(hipStreamWaitEvent(st, db->join, 0));
@@ -704,7 +701,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
         TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * rows_alloc * 512));
     // wave-per-pair scratch: one slot per wave of whichever kernel runs the long list
     const int64_t long_slots = L.fused_long ? (int64_t)L.grid_inter * plan.waves
-                                            : (int64_t)L.long_grid() * kIntraWaves;
+                                            : (int64_t)L.grid_long * kIntraWaves;
     const int64_t intra_slots = std::max<int64_t>(long_slots, L.grid_ovf);
     TRY(db->w_scr_intra.reserve((size_t)intra_slots * intra_scratch_rows(db) * 8));
     if (k > 0) {
@@ -1139,9 +1136,7 @@ int server_setup(sw_server *s) {
         TRY(s->d_scr_inter.reserve((size_t)std::max(s->L.grid_inter, s->grid_fused) * W *
                                    s->scr_rows * 512));
     const int64_t islots = std::max<int64_t>(
-        std::max<int64_t>(
-            (int64_t)std::max(s->L.grid_long, s->L.grid_packed) * kIntraWaves,
-            (int64_t)s->grid_fused * W),
+        std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, (int64_t)s->grid_fused * W),
         s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
     // a pass may hold lane-per-subject and wave-per-pair items together
@@ -1284,7 +1279,6 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
                        ? (int)std::min<int64_t>(n_inter + n_intra, s->grid_fused)
                        : (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
     L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
-    L.grid_packed = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_packed);
     TRY(enqueue_pass(db, L, pb, st, nullptr, nullptr, true));
     // requests that visited their last position get top-k
     std::vector<int32_t> done_rows;
