@@ -595,7 +595,8 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         oa.item_ids = b.ovf_id;
         oa.n_items_dev = b.counters + 1;
         oa.counter = b.counters + 3;
-        HIPX(launch_intra(oa, 16, 1, L.grid_ovf, st));
+        // the launch's own columns per lane: a short query's pass is narrower
+        HIPX(launch_intra(oa, L.Ti, 1, L.grid_ovf, st));
     }
     return SW_OK;
 }
