@@ -1274,6 +1274,11 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.scr_rows = s->scr_rows;
     pb.scr_intra = s->d_scr_intra.as<int32_t>();
     Launch L = s->L;
+    // columns per lane of the wave-per-pair work (long list, recompute) from
+    // this pass's longest query; setup sized everything for the widest
+    int64_t max_q = 1;
+    for (const PassWork &w : work) max_q = std::max(max_q, w.qlen);
+    L.Ti = intra_T_for(max_q);
     L.fused_long = it.fused && n_intra > 0;
     L.packed_long = !it.fused && it.per_item == 2 * kIntraWaves;
     L.grid_inter = L.fused_long
