@@ -326,7 +326,8 @@ int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> 
         const double rows = (double)db->inter_padded_rows / kGroup;
         const double share = strips * rows / std::max(resident_waves, 1) / max_strips;
         const int64_t rows_cut = std::max<int64_t>(1024, (int64_t)share);
-        g_cut = std::upper_bound(db->grp_rows.begin(), db->grp_rows.end(), (int32_t)std::min<int64_t>(rows_cut, INT32_MAX)) -
+        const int32_t cut32 = (int32_t)std::min<int64_t>(rows_cut, INT32_MAX);
+        g_cut = std::upper_bound(db->grp_rows.begin(), db->grp_rows.end(), cut32) -
                 db->grp_rows.begin();
         if (g_cut < db->n_groups) g_cut = g_cut / W * W;
     }
