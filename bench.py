@@ -11,11 +11,15 @@ It is opened once, as the paper's offline index is built once.
 
 Also measured in the same run, as sub-objects of the JSON line:
   batched: 512 queries (50..1,500) against 500k subjects in one fused launch
-           replayed from a captured HIP graph;
+           replayed from a captured HIP graph (with the autotuner run on the
+           batch's query lengths first), and
+           the same 512 queries as 512 plain top-k searches of that database;
   served:  Poisson arrivals against a resident 5M-subject database
-           (continuous batching), p50/p99 latency and sustained GCUPS, at the
-           configured 50 queries/s (over a short window) and at ~70% of the
-           measured capacity.
+           (continuous batching), p50/p99 latency and sustained GCUPS, at
+           50 queries/s over a short window (labelled with its window and
+           request count; the full 120 s configuration is its own run,
+           --only-served --serve-seconds 120) and at ~70% of the measured
+           capacity.
 
 Prints one JSON line.  GCUPS = sum|Q| * sum|S| / seconds.
 """
@@ -44,6 +48,9 @@ PEAK_HALF_OPS = 2 * PEAK_LANE_OPS                    # packed 16-bit lane-ops/s 
 # per four columns, and one max3 per two cells for the running best.
 OPS_PER_CELL = 5.75
 PEAK_GCUPS_F16X2 = PEAK_HALF_OPS / OPS_PER_CELL / 1e9
+# The textbook count of Eq. 1 per cell with E and F floored at 0 (add, max3 for
+# H, max for the best, sub for H - beta, sub + max3 for E, sub + max3 for F).
+OPS_PER_CELL_TEXTBOOK = 8
 
 
 def log(msg):
@@ -75,8 +82,29 @@ def measured_traffic(workload, plan_overridden):
     return rec["traffic_bytes_per_launch"]
 
 
+def host_cpu():
+    """Model, sockets and physical cores of this host (lscpu)."""
+    info = {}
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = dict(line.split(":", 1) for line in out.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        per = int(kv.get("Core(s) per socket", "0") or 0)
+        info = {"model": kv.get("Model name", "?"), "sockets": sockets,
+                "physical_cores": sockets * per,
+                "threads_per_core": int(kv.get("Thread(s) per core", "0") or 0),
+                "logical_cpus": int(kv.get("CPU(s)", "0") or 0)}
+    except Exception as e:   # lscpu missing: report what os says
+        info = {"model": "?", "error": str(e)}
+    info["usable_cpus"] = len(os.sched_getaffinity(0))
+    return info
+
+
 def cpu_baseline(workload, res, off, queries, M, target_s=15.0):
-    """The oracle on the host cores, on a bounded sample of the same workload."""
+    """The oracle on the host cores, on a bounded sample of the same workload:
+    once with its default OpenMP threads, once on one core."""
     import oracle
     orc = oracle.load()
     threads = orc.max_threads()
@@ -98,10 +126,24 @@ def cpu_baseline(workload, res, off, queries, M, target_s=15.0):
     for q in queries:
         orc.search_subset(q, res, off, sample, M, workload.alpha, workload.beta)
     dt = time.perf_counter() - t
+    # one core: every query against a random part of the same sample, sized
+    # for about a third of the target time
+    n1 = int(np.clip(len(sample) * (target_s / 3) / max(dt, 1e-6) / max(threads, 1), 16,
+                     len(sample)))
+    s1 = np.sort(rng.choice(sample, size=n1, replace=False))
+    cells1 = sum_q * int(lens[s1].sum())
+    t = time.perf_counter()
+    for q in queries:
+        orc.search_subset(q, res, off, s1, M, workload.alpha, workload.beta, nthreads=1)
+    dt1 = time.perf_counter() - t
     return {"value": round(cells / dt / 1e9, 3), "unit": "GCUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"all {len(queries)} queries vs {n_sub} random subjects of the same database "
-                      f"({cells:.3e} cells, {dt:.1f} s)"}
+                      f"({cells:.3e} cells, {dt:.1f} s)",
+            "one_core": {"value": round(cells1 / dt1 / 1e9, 3), "unit": "GCUPS", "cores": 1,
+                         "sample": f"all {len(queries)} queries vs {n1} of those subjects "
+                                   f"({cells1:.3e} cells, {dt1:.1f} s)"},
+            "host": host_cpu()}
 
 
 def run_plain(args, swmi, sd, torch):
@@ -178,20 +220,58 @@ def run_plain(args, swmi, sd, torch):
         "kernel_gcups": round(cells_step * args.steps /
                               (sum(s["kernel_ms"] for s in all_sts) / 1e3) / 1e9, 2),
         "recomputed_pairs_per_step": sum(s["recomputed_pairs"] for s in all_sts) // max(args.steps, 1),
+        # the exact int32 recompute of flagged pairs: its device time per step
+        # and its share of all device time of the steps
+        "recompute_ms_per_step": round(sum(max(s["recompute_ms"], 0.0) for s in all_sts) /
+                                       max(args.steps, 1), 3),
+        "recompute_share": round(sum(max(s["recompute_ms"], 0.0) for s in all_sts) /
+                                 max(sum(s["kernel_ms"] for s in all_sts), 1e-9), 5),
     }
     if align:
         out["align_topk"] = align
     if inter:
+        # One launch of the lane-per-subject kernel per query.  Its cells: the
+        # lane-per-subject cells, plus the long list's when that ran inside the
+        # same launch (fused; its int32 cells are counted at the same rate,
+        # which understates the launch's work).
         avg_launch_ms = sum(s["inter_ms"] for s in inter) / len(inter)
-        ops_per_launch = OPS_PER_CELL * sum(s["inter_cells"] for s in inter) / len(inter)
-        achieved = ops_per_launch / (avg_launch_ms / 1e3) / 1e12
+        cells_launch = sum(s["cells"] if s["fused_long"] else s["inter_cells"]
+                           for s in inter) / len(inter)
         peak = PEAK_HALF_OPS / 1e12
+        achieved = OPS_PER_CELL * cells_launch / (avg_launch_ms / 1e3) / 1e12
+        textbook = OPS_PER_CELL_TEXTBOOK * cells_launch / (avg_launch_ms / 1e3) / 1e12
         traffic = measured_traffic(w.name, bool(args.tier or args.strip or args.waves))
-        out["roofline"] = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
-                           "unit": "Tops/s", "frac": round(achieved / peak, 4),
-                           "traffic": round(traffic) if traffic else None,
-                           "traffic_unit": "bytes per launch", "kernel": "inter_kernel (f16x2)",
-                           "ops_per_cell": OPS_PER_CELL, "avg_launch_ms": round(avg_launch_ms, 3)}
+        out["roofline"] = {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "Tops/s", "frac": round(achieved / peak, 4),
+            "traffic": round(traffic) if traffic else None,
+            "traffic_unit": "bytes per launch", "kernel": "inter_kernel (f16x2)",
+            "ops_per_cell": OPS_PER_CELL, "cells_per_launch": round(cells_launch),
+            "avg_launch_ms": round(avg_launch_ms, 3),
+            "basis": "packed 16-bit VALU lane-ops of the frame form the kernel evaluates "
+                     "(5.75 per cell) over the packed 16-bit peak",
+            "textbook_basis": {
+                "ops_per_cell": OPS_PER_CELL_TEXTBOOK, "achieved": round(textbook, 3),
+                "peak": round(peak, 2), "frac": round(textbook / peak, 4),
+                "why_frac_can_exceed_1": "the count of 8 takes alpha off E and F at every cell; "
+                                         "the frame form stores values offset by alpha per row "
+                                         "and per column within groups of 4, so it needs 5.75"}}
+    longs = [s for s in all_sts if s["inter_cells"] == 0 and s["long_ms"] > 0]
+    if not inter and longs:
+        # every subject on the wave-per-pair kernel (long_tail): its own launch,
+        # timed between the events around it
+        avg_ms = sum(s["long_ms"] for s in longs) / len(longs)
+        cells_launch = sum(s["cells"] for s in longs) / len(longs)
+        peak = PEAK_HALF_OPS / 1e12
+        achieved = OPS_PER_CELL * cells_launch / (avg_ms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "traffic_unit": "bytes per launch", "kernel": "intra2_kernel (f16x2)",
+            "ops_per_cell": OPS_PER_CELL, "cells_per_launch": round(cells_launch),
+            "avg_launch_ms": round(avg_ms, 3),
+            "basis": "packed 16-bit VALU lane-ops of the frame form (5.75 per cell) over the "
+                     "packed 16-bit peak"}
     return out, (w, res, off, queries, M)
 
 
@@ -218,6 +298,9 @@ def run_align(args, swmi, db, w, res, off, queries, M):
 
 
 def run_batched(args, swmi, sd, torch):
+    """The 512-query batch in one graph-replayed launch, after the autotuner has
+    timed plans for the batch's query lengths on this database, against the
+    same 512 queries searched one at a time (top-10 each) on the same handle."""
     w = sd.WORKLOADS["batched"]
     res, off = w.db()
     queries = w.queries()
@@ -226,6 +309,13 @@ def run_batched(args, swmi, sd, torch):
     sptr = torch.cuda.current_stream().cuda_stream
     cells = sum(len(q) for q in queries) * int(len(res))
     log(f"[bench] batched: {len(queries)} queries x {len(off) - 1} subjects ({cells:.3e} cells)")
+    t0 = time.perf_counter()
+    with tempfile.TemporaryDirectory() as td:
+        cache = os.path.join(td, "plans.json")
+        swmi.sw_db_autotune(db.h, M, w.alpha, w.beta, [len(q) for q in queries], cache)
+        tuned = [[e["bucket"], e["tier"], e["strip"], e["waves"], e["gcups"]]
+                 for e in json.load(open(cache))["entries"]] if os.path.exists(cache) else []
+    log(f"[bench] batched: autotuned in {time.perf_counter() - t0:.1f}s: {tuned}")
     swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, 10, stream=sptr)   # warmup + capture
     torch.cuda.synchronize()
     steps = max(1, args.batched_steps)
@@ -237,49 +327,95 @@ def run_batched(args, swmi, sd, torch):
         kern += st["kernel_ms"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
-    db.close()
     g = cells * steps / dt / 1e9
-    log(f"[bench] batched done: {g:.1f} GCUPS")
+    log(f"[bench] batched done: {g:.1f} GCUPS; the same queries as plain searches")
+    # the same 512 queries, one sw_db_topk call each (plans from the same table)
+    for q in queries[:8]:
+        swmi.sw_db_topk(db.h, q, M, w.alpha, w.beta, 10, stream=sptr)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for q in queries:
+        swmi.sw_db_topk(db.h, q, M, w.alpha, w.beta, 10, stream=sptr)
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t
+    db.close()
+    g_plain = cells / dt_plain / 1e9
+    log(f"[bench] plain: {g_plain:.1f} GCUPS")
     return {"workload": w.name, "queries": len(queries), "subjects": len(off) - 1,
             "residues": int(len(res)), "k": 10, "graphed": bool(st["graphed"]),
             "gcups": round(g, 2), "kernel_gcups": round(cells * steps / (kern / 1e3) / 1e9, 2),
             "frac_of_f16x2_peak_gcups": round(g / PEAK_GCUPS_F16X2, 4),
             "ms_per_batch": round(dt / steps * 1e3, 1), "tier": st["tier"], "strip": st["strip"],
-            "waves": st["waves"]}
+            "waves": st["waves"], "tuned_plans": tuned,
+            "plain_same_queries": {"calls": len(queries), "gcups": round(g_plain, 2),
+                                   "ms_total": round(dt_plain * 1e3, 1)},
+            "vs_plain_gcups": round(g / g_plain, 3)}
 
 
-def serve_phase(swmi, srv, M, alpha, beta, queries, arrivals, total_res):
-    """Open-loop arrivals; returns latency percentiles and sustained GCUPS."""
-    lat, qms = [], []
-    cells = 0
+def serve_phase(swmi, srv, M, alpha, beta, queries, arrivals, total_res, collectors=32):
+    """Open-loop arrivals; latency percentiles over every request (the drain
+    after the last arrival included), sustained GCUPS and the backlog (requests
+    submitted and not yet complete) once a second.  Latencies are the
+    library's own submit-to-result times, so a busy collector does not skew
+    them."""
+    import queue
+    lat, qms, done_at = [], [], []
     lock = threading.Lock()
+    tickets = queue.Queue()
     t0 = time.perf_counter()
 
-    def collector(t):
-        _, _, st = swmi.sw_server_wait(srv, t, 10)
-        with lock:
-            lat.append(st["total_ms"])
-            qms.append(st["queue_ms"])
+    def collector():
+        while True:
+            item = tickets.get()
+            if item is None:
+                return
+            t, t_sub = item
+            _, _, st = swmi.sw_server_wait(srv, t, 10)
+            with lock:
+                lat.append(st["total_ms"])
+                qms.append(st["queue_ms"])
+                done_at.append(t_sub + st["total_ms"] / 1e3)
 
-    threads = []
+    pool = [threading.Thread(target=collector) for _ in range(collectors)]
+    for th in pool:
+        th.start()
+    cells = 0
+    submitted_at = []
+    next_log = 10.0
     for q, a in zip(queries, arrivals):
         now = time.perf_counter() - t0
         if a > now:
             time.sleep(a - now)
+        t_sub = time.perf_counter() - t0
         t = swmi.sw_server_submit(srv, q, M, alpha, beta, 10)
+        submitted_at.append(t_sub)
         cells += len(q) * total_res
-        th = threading.Thread(target=collector, args=(t,))
-        th.start()
-        threads.append(th)
-    for th in threads:
-        th.join()
+        tickets.put((t, t_sub))
+        if t_sub >= next_log:
+            log(f"[bench] serving: {len(submitted_at)} submitted at {t_sub:.0f}s")
+            next_log += 10.0
+    for _ in pool:
+        tickets.put(None)
+    while any(th.is_alive() for th in pool):
+        for th in pool:
+            th.join(timeout=10.0)
+        log(f"[bench] serving: draining, {len(done_at)} of {len(submitted_at)} done "
+            f"at {time.perf_counter() - t0:.0f}s")
     span = time.perf_counter() - t0
     lat = np.array(lat)
-    return {"requests": len(queries), "offered_per_s": round(len(queries) / max(arrivals[-1], 1e-9), 2),
+    sub = np.sort(np.array(submitted_at))
+    fin = np.sort(np.array(done_at))
+    grid = np.arange(0.0, span + 1.0, 1.0)
+    backlog = (np.searchsorted(sub, grid, side="right") -
+               np.searchsorted(fin, grid, side="right")).tolist()
+    return {"requests": len(queries), "window_s": round(float(arrivals[-1]), 2) if len(arrivals) else 0,
+            "offered_per_s": round(len(queries) / max(arrivals[-1], 1e-9), 2),
             "p50_ms": round(float(np.percentile(lat, 50)), 1),
             "p99_ms": round(float(np.percentile(lat, 99)), 1),
+            "max_ms": round(float(lat.max()), 1),
             "mean_queue_ms": round(float(np.mean(qms)), 1),
-            "sustained_gcups": round(cells / span / 1e9, 1), "span_s": round(span, 2)}
+            "sustained_gcups": round(cells / span / 1e9, 1), "span_s": round(span, 2),
+            "backlog_per_s": backlog}
 
 
 def run_served(args, swmi, sd, torch):
@@ -294,12 +430,18 @@ def run_served(args, swmi, sd, torch):
     srv = swmi.sw_server_start(db.h, memory_budget=8 << 30, max_active=64)
     out = {"workload": w.name, "subjects": len(off) - 1, "residues": total, "k": 10}
     try:
-        # phase 1: the configured rate (50 queries/s) over a short window
+        # phase 1: the configured rate (50 queries/s) over args.serve_seconds;
+        # the configuration itself is 120 s (--only-served --serve-seconds 120)
         arr = sd.poisson_arrivals(50.0, args.serve_seconds, seed=sd.SEED_ARRIVALS)
         qs = sd.serving_queries(len(arr), seed=sd.SEED_QUERIES + 20)
-        log(f"[bench] serving phase 1: {len(arr)} requests at 50/s")
+        log(f"[bench] serving phase 1: {len(arr)} requests at 50/s over {args.serve_seconds:g}s")
         p1 = serve_phase(swmi, srv, M, w.alpha, w.beta, qs, arr, total)
+        p1["what"] = ("the configured 50/s for 120 s" if args.serve_seconds >= 120 else
+                      f"50/s over a {args.serve_seconds:g} s window only (the configuration is "
+                      "120 s; see the committed served record)")
         out["at_50_per_s"] = p1
+        if args.only_served:
+            return out
         # capacity from phase 1, then ~70% of it
         mean_cells = float(np.mean([len(q) for q in qs])) * total
         rate = max(0.5, 0.7 * p1["sustained_gcups"] * 1e9 / mean_cells)
@@ -335,6 +477,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
+    ap.add_argument("--only-served", action="store_true",
+                    help="run only the served workload's 50/s phase and print its record")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device three times (the reference "
                          "kernel that scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -360,11 +504,14 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copied {n} bytes device to device, 3 times")
         return
+    if args.only_served:
+        rec = run_served(args, swmi, sd, torch)
+        print(json.dumps({"metric": "p50/p99 query latency (served)", "unit": "ms",
+                          "data": "synthetic", "served": rec}), flush=True)
+        return
     out, (w, res, off, queries, M) = run_plain(args, swmi, sd, torch)
     if not args.no_batched and args.workload == "plain_scale":
-        b = run_batched(args, swmi, sd, torch)
-        b["vs_plain_gcups"] = round(b["gcups"] / out["value"], 3)
-        out["batched"] = b
+        out["batched"] = run_batched(args, swmi, sd, torch)
     if not args.no_served and args.workload == "plain_scale":
         out["served"] = run_served(args, swmi, sd, torch)
     if not args.no_cpu_baseline:

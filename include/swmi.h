@@ -110,6 +110,10 @@ typedef struct sw_stats {
     int32_t graphed;          /* 1 if the device work ran as a captured HIP graph */
     int32_t fused_long;       /* 1 if the long list (wave-per-pair, int32) ran inside the
                                  lane-per-subject kernel's work queue, 0 if as its own kernel */
+    double  recompute_ms;     /* device time of the exact int32 recompute of flagged pairs
+                                 (-1 when the work ran as a graph) */
+    double  long_ms;          /* device time of the wave-per-pair kernel when it ran alone
+                                 (no lane-per-subject work in the call); -1 otherwise */
 } sw_stats;
 
 /* Open a database (section III, stage ii: sequences are sorted by length and
@@ -152,7 +156,11 @@ int sw_db_search_dev(sw_db *db, const uint8_t *query, int32_t qlen, const sw_sco
 int sw_db_topk(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
                int32_t k, int32_t *top_scores, int64_t *top_idx, void *hip_stream);
 
-/* Many queries in one fused launch over the database.
+/* Many queries in one fused launch over the database.  No passage of the
+ * paper defines a batched call: SWAPHI searches one query at a time.  This is
+ * the GPU form of its work distribution (section III.A: sequence profiles
+ * handed to threads by a guided schedule), with the (query, subject group)
+ * pairs of all queries in one persistent work queue.
  *   q_res / q_off: nq queries concatenated, q_off has nq + 1 entries
  *   top_scores / top_idx: nq * k (row per query), same order rules as sw_db_topk
  *   all_scores: NULL, or nq * n_seqs int32 (row per query, database order) */
@@ -197,24 +205,40 @@ typedef struct sw_alignment {
  * Device memory: one byte per cell of the pairs aligned together (batches of
  * up to 1 GiB; a single subject needing more than 16 GiB fails with
  * SW_ENOMEM).  Synchronous on the database's own stream. */
-int sw_db_align(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring *sc,
+int sw_db_align(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
                 const int64_t *ids, int32_t n_ids, sw_alignment *out, uint32_t *ops,
                 int64_t ops_cap, int64_t *ops_needed);
 
 /* Run the autotuner: for each query-length bucket of the given lengths, time
  * every candidate plan on a sample of this database's blocks, re-time the two
  * fastest on the whole database (best of two runs) and keep the faster.  If
- * cache_path is non-NULL the table is read from / written to that JSON file. */
+ * cache_path is non-NULL the table is read from / written to that JSON file.
+ * No passage of the paper defines it; it plays the part of the paper's
+ * empirical choices of thread count and schedule (section III.A) and of the
+ * score profile's depth (section III.B.3). */
 int sw_db_autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_qlens,
                    const char *cache_path);
 
-/* ---- serving (continuous batching over a resident database) ---- */
+/* ---- serving (continuous batching over a resident database) ----
+ * No passage of the paper defines a server: SWAPHI is a batch program.  The
+ * server keeps the database resident (the paper re-offloads it chunk by chunk
+ * per run, section III, whose fixed costs it found to dominate small
+ * workloads, section IV.C) and coalesces the requests in flight into shared
+ * passes over database chunks. */
 
 typedef struct sw_server_opts {
-    int64_t memory_budget;   /* bytes of device memory for admitted requests' profiles and
-                                per-request state; 0 = 1 GiB */
+    int64_t memory_budget;   /* bytes of per-request device state the admitted requests may
+                                hold together: each request is charged its query profile
+                                ((alphabet + 1) x qlen rounded up to 32 bytes) and its top-k
+                                (12 x k bytes).  A request that does not fit waits; smaller
+                                later ones may pass it until it has waited 2 s.  The score
+                                rows (max_active x n_seqs x 4 bytes) and the pass workspaces
+                                are allocated once, at start, outside this budget.
+                                0 = 1 GiB */
     int32_t max_active;      /* requests admitted at once (each pass serves the ones with the
-                                least work left first; the oldest always advances); 0 = 64 */
+                                least work left first; the oldest always advances).  Requests
+                                whose alpha exceeds 28 run in an int16 sub-pass of each pass,
+                                the others in the fp16 tier.  0 = 64 */
     int32_t queue_capacity;  /* waiting requests before submit returns SW_EBUSY; 0 = 65536 */
     int32_t chunk_groups;    /* database chunk (one scan position), in groups of 128 subjects;
                                 0 = chosen by the server (1/16 of the lane-per-subject groups) */
@@ -226,7 +250,7 @@ typedef struct sw_req_stats {
     double total_ms;   /* submit -> result ready */
     int64_t cells;     /* |Q| * sum |S| */
     int32_t passes;    /* server passes (launches) this request took part in */
-    int32_t reserved;
+    int32_t shared_passes;   /* of those, passes that also served another request */
 } sw_req_stats;
 
 /* Start a server over an open database.  The database must outlive the server

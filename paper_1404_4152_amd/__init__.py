@@ -50,7 +50,8 @@ class sw_stats(ctypes.Structure):
                 ("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("inter_ms", ctypes.c_double), ("tier", ctypes.c_int32), ("strip", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("graphed", ctypes.c_int32),
-                ("fused_long", ctypes.c_int32)]
+                ("fused_long", ctypes.c_int32), ("recompute_ms", ctypes.c_double),
+                ("long_ms", ctypes.c_double)]
 
 
 class sw_alignment(ctypes.Structure):
@@ -67,7 +68,8 @@ class sw_server_opts(ctypes.Structure):
 
 class sw_req_stats(ctypes.Structure):
     _fields_ = [("queue_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("cells", ctypes.c_int64), ("passes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("cells", ctypes.c_int64), ("passes", ctypes.c_int32),
+                ("shared_passes", ctypes.c_int32)]
 
 
 _P = ctypes.POINTER
@@ -88,7 +90,7 @@ SIGNATURES = {
     "sw_db_search_batch": (ctypes.c_int, [_vp, ctypes.c_int32, _u8p, _i64p, _P(sw_scoring),
                                           ctypes.c_int32, _i32p, _i64p, _i32p, _vp]),
     "sw_db_autotune": (ctypes.c_int, [_vp, _P(sw_scoring), _i32p, ctypes.c_int32, ctypes.c_char_p]),
-    "sw_db_align": (ctypes.c_int, [_vp, _u8p, ctypes.c_int64, _P(sw_scoring), _i64p, ctypes.c_int32,
+    "sw_db_align": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), _i64p, ctypes.c_int32,
                                    _P(sw_alignment), _P(ctypes.c_uint32), ctypes.c_int64, _i64p]),
     "sw_server_start": (ctypes.c_int, [_vp, _P(sw_server_opts), _P(_vp)]),
     "sw_server_submit": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), ctypes.c_int32,

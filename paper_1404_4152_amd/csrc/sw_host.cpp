@@ -230,7 +230,7 @@ struct sw_db {
     HostBuf h_stage;
     DevBuf w_al_meta, w_al_dir, w_al_ops, w_al_scr;   // sw_db_align workspaces
     HostBuf h_al;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     std::mutex mu;
     sw_search_opts opts{};
     sw_stats last{};
@@ -505,7 +505,8 @@ struct PassBufs {
 
 // Enqueue one pass: counter reset (a fill kernel, safe under graph capture),
 // lane-per-subject kernel, wave-per-pair kernel on the long list, exact
-// recompute of flagged lanes.  Optional events bracket the first kernel.
+// recompute of flagged lanes.  Optional events bracket the first kernel;
+// ev_r (optional) is recorded just before the recompute.
 // The long list's makespan is its longest pair, so it should start at once
 // and share the GPU with the lane-per-subject work:
 //  * L.fused_long: its items run first in the lane-per-subject kernel's own
@@ -514,7 +515,8 @@ struct PassBufs {
 //    launched before the lane-per-subject kernel (the other order measured
 //    slower and erratic), and joins before the recompute.
 int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_t st,
-                 hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr, bool overlap = false) {
+                 hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr, bool overlap = false,
+                 hipEvent_t ev_r = nullptr) {
     HIPX(launch_fill_i32(b.counters, 0, 4, st));
     const bool fused = L.fused_long && b.n_intra > 0;
     const bool fork = overlap && !fused && b.n_inter > 0 && b.n_intra > 0;
@@ -590,6 +592,7 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         else HIPX(launch_intra(la, L.Ti, kIntraWaves, L.grid_long, st));
     }
     if (fork) HIPX(hipStreamWaitEvent(st, db->join, 0));
+    if (ev_r) HIPX(hipEventRecord(ev_r, st));
     if (b.n_inter > 0 || (packed_long && b.n_intra > 0)) {
         IntraArgs oa = ia;
         oa.item_q = b.ovf_q;
@@ -762,7 +765,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
 
     auto enqueue_all = [&](hipStream_t s, bool events) -> int {
         TRY(enqueue_pass(db, L, pb, s, events ? db->ev[0] : nullptr, events ? db->ev[1] : nullptr,
-                         true));
+                         true, events ? db->ev[4] : nullptr));
         if (events) HIPX(hipEventRecord(db->ev[2], s));
         if (k > 0)
             HIPX(launch_topk(pb.scores, n, nq, nullptr, k, topk_work(db->w_topk.p, nq, k), d_ts,
@@ -826,9 +829,14 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     HIPX(hipMemcpyAsync(ctr_h, pb.counters, 16, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
 
-    float ms_k = 0, ms_i = -1;
+    float ms_k = 0, ms_i = -1, ms_r = -1, ms_l = -1;
     HIPX(hipEventElapsedTime(&ms_k, db->ev[0], db->ev[2]));
-    if (!graphed) HIPX(hipEventElapsedTime(&ms_i, db->ev[0], db->ev[1]));
+    if (!graphed) {
+        HIPX(hipEventElapsedTime(&ms_i, db->ev[0], db->ev[1]));
+        HIPX(hipEventElapsedTime(&ms_r, db->ev[4], db->ev[2]));
+        // the wave-per-pair kernel alone on the stream, between the two
+        if (n_inter == 0 && n_intra > 0) HIPX(hipEventElapsedTime(&ms_l, db->ev[1], db->ev[4]));
+    }
     sw_stats &s = db->last;
     s = sw_stats{};
     s.cells = sum_qlen * db->total_res;
@@ -844,6 +852,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     s.intra_pairs = (int64_t)long_ids.size() * nq;
     s.kernel_ms = ms_k;
     s.inter_ms = ms_i;
+    s.recompute_ms = ms_r;
+    s.long_ms = ms_l;
     s.total_ms = now_ms() - t_start;
     s.tier = plan.tier;
     s.strip = plan.strip;
@@ -1018,6 +1028,7 @@ struct Request {
     int32_t next = 0;        // next database position to visit
     int32_t remaining = 0;   // database positions still to visit
     int32_t passes = 0;      // passes (launches) this request took part in
+    int32_t shared = 0;      // of those, passes that also served another request
     int rc = SW_OK;
     bool done = false;
     std::vector<int32_t> top_s;
@@ -1029,7 +1040,9 @@ struct Request {
 struct sw_server {
     sw_db *db = nullptr;
     sw_server_opts opts{};
-    Plan plan;
+    Plan plan;                   // requests with alpha <= kFrameMaxAlpha (fp16 unless overridden)
+    Plan plan16;                 // requests with larger alpha: the int16 tier, same waves
+    bool split_tiers = false;    // high-alpha requests run in their own int16 sub-pass
     int64_t blocks = 0, chunk_blocks = 0, n_chunks = 0, n_pos = 0;
     std::vector<SchedPos> pos;   // per database position: residues, items, subjects
     int64_t pass_cells = 0;      // work a pass aims for (cells)
@@ -1045,7 +1058,8 @@ struct sw_server {
     DevBuf d_meta, d_scores, d_ovf, d_counters, d_scr_inter, d_scr_intra, d_items, d_topk, d_top,
         d_rows;
     HostBuf h_items, h_meta, h_top, h_rows;
-    Launch L;
+    Launch L, L16;
+    size_t items_half = 0;       // bytes of item staging per sub-pass (h_items holds two)
     bool fuse = false;           // int32 long-list items may run in the lane-per-subject kernel
     int grid_fused = 0;          // resident workgroups of that fused kernel
     // host state
@@ -1069,6 +1083,19 @@ int server_setup(sw_server *s) {
     HIPX(hipSetDevice(db->device));
     s->plan = plan_for(db, 512, 0);
     const int W = s->plan.waves;
+    // A request whose alpha would lower the fp16 ceiling past kFrameMaxAlpha
+    // runs in an int16 sub-pass of its own (the planner's choice for a plain
+    // search), over the same positions: the same waves per workgroup, so the
+    // same blocks.
+    s->plan16 = s->plan;
+    s->split_tiers = db->opts.tier == 0 && s->plan.tier == TIER_F16X2;
+    if (s->split_tiers) {
+        s->plan16.tier = TIER_I16X2;
+        s->plan16.strip = 32;
+        s->plan16.thr = kThrI16;
+        if (db->opts.sat_threshold > 0 && db->opts.sat_threshold < s->plan16.thr)
+            s->plan16.thr = db->opts.sat_threshold;
+    }
     {
         // route as if half the slots held 400-residue queries
         const int slots = s->opts.max_active > 0 ? s->opts.max_active : 64;
@@ -1123,8 +1150,11 @@ int server_setup(sw_server *s) {
     const int64_t intra_items = (int64_t)s->slots * nlblk;
     s->L = launch_config(db, s->plan, 1 << 14, std::max<int64_t>(inter_items, 1),
                          std::max<int64_t>(intra_items, 1));
+    s->L16 = launch_config(db, s->plan16, 1 << 14, std::max<int64_t>(inter_items, 1),
+                           std::max<int64_t>(intra_items, 1));
     s->fuse = fuse_ok(db, s->plan, s->L.Ti);
     s->grid_fused = s->fuse ? inter_max_grid(db->R, s->plan.tier, s->plan.strip, W, s->L.Ti) : 0;
+    const int grid_inter_max = std::max(s->L.grid_inter, s->L16.grid_inter);
     TRY(s->d_meta.reserve((size_t)s->slots * 24 + 256));
     TRY(s->h_meta.reserve((size_t)s->slots * 24 + 256));
     std::memset(s->h_meta.p, 0, (size_t)s->slots * 24 + 256);
@@ -1135,16 +1165,17 @@ int server_setup(sw_server *s) {
     TRY(s->d_counters.reserve(256));
     s->scr_rows = s->g_cut > 0 ? db->grp_rows[s->g_cut - 1] : 0;
     if (s->g_cut > 0)
-        TRY(s->d_scr_inter.reserve((size_t)std::max(s->L.grid_inter, s->grid_fused) * W *
+        TRY(s->d_scr_inter.reserve((size_t)std::max(grid_inter_max, s->grid_fused) * W *
                                    s->scr_rows * 512));
     const int64_t islots = std::max<int64_t>(
         std::max<int64_t>((int64_t)s->L.grid_long * kIntraWaves, (int64_t)s->grid_fused * W),
         s->L.grid_ovf);
     TRY(s->d_scr_intra.reserve((size_t)islots * intra_scratch_rows(db) * 8));
     // a pass may hold lane-per-subject and wave-per-pair items together
-    const size_t items_bytes = (size_t)(inter_items * 2 + intra_items * (1 + per) + 64) * 4;
-    TRY(s->d_items.reserve(items_bytes));
-    TRY(s->h_items.reserve(items_bytes));
+    // (two sub-passes: fp16 requests, then int16 ones, each with its own half)
+    s->items_half = (size_t)round_up((inter_items * 2 + intra_items * (1 + per) + 64) * 4, 256);
+    TRY(s->d_items.reserve(2 * s->items_half));
+    TRY(s->h_items.reserve(2 * s->items_half));
     TRY(s->d_topk.reserve(topk_work_bytes(s->slots, SW_MAX_K)));
     TRY(s->d_top.reserve((size_t)s->slots * SW_MAX_K * 12));
     TRY(s->h_top.reserve((size_t)s->slots * SW_MAX_K * 12));
@@ -1154,26 +1185,37 @@ int server_setup(sw_server *s) {
 }
 
 // Admit waiting requests in arrival order while a slot and the memory budget
-// allow.  Called with s->mu held; returns the newly admitted requests.
+// allow.  A request that does not fit the budget yet lets later, smaller ones
+// pass it, until it has waited kAdmitAgeMs; from then on nothing passes it, so
+// it is admitted as soon as enough admitted work completes.  Called with
+// s->mu held; returns the newly admitted requests.
+constexpr double kAdmitAgeMs = 2000.0;
+
 std::vector<std::shared_ptr<Request>> admit(sw_server *s) {
     std::vector<std::shared_ptr<Request>> out;
-    while (!s->waiting.empty()) {
-        auto &r = s->waiting.front();
+    const double now = now_ms();
+    for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+        auto &r = *it;
         int slot = -1;
         for (int i = 0; i < s->slots; ++i)
             if (!s->active[i]) {
                 slot = i;
                 break;
             }
-        if (slot < 0 || s->used_bytes + r->bytes > s->opts.memory_budget) break;
+        if (slot < 0) break;
+        if (s->used_bytes + r->bytes > s->opts.memory_budget) {
+            if (now - r->t_submit >= kAdmitAgeMs) break;
+            ++it;
+            continue;
+        }
         r->slot = slot;
         r->next = 0;
         r->remaining = (int32_t)s->n_pos;
-        r->t_admit = now_ms();
+        r->t_admit = now;
         s->used_bytes += r->bytes;
         s->active[slot] = r;
         out.push_back(r);
-        s->waiting.pop_front();
+        it = s->waiting.erase(it);
     }
     return out;
 }
@@ -1243,28 +1285,18 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     }
     std::sort(riders.begin(), riders.end());
     riders.erase(std::unique(riders.begin(), riders.end()), riders.end());
-    Items it;
-    build_work_items(db, s->plan, work, s->long_ids, s->fuse, it);
-    const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
-    int32_t *hi = s->h_items.as<int32_t>();
-    std::memcpy(hi, it.inter_q.data(), n_inter * 4);
-    std::memcpy(hi + n_inter, it.inter_g.data(), n_inter * 4);
-    std::memcpy(hi + 2 * n_inter, it.intra_q.data(), n_intra * 4);
-    std::memcpy(hi + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * it.per_item * 4);
-    const size_t ib = (size_t)(2 * n_inter + n_intra * (1 + it.per_item)) * 4;
-    if (ib) HIPX(hipMemcpyAsync(s->d_items.p, hi, ib, hipMemcpyHostToDevice, st));
+    // Requests whose alpha is past the fp16 tier's range run in an int16
+    // sub-pass after the fp16 one (same stream, so they use the counters and
+    // the overflow list one after the other).
+    std::vector<PassWork> sub[2];
+    for (const PassWork &w : work)
+        sub[s->split_tiers && s->active[w.slot]->alpha > kFrameMaxAlpha ? 1 : 0].push_back(w);
     PassBufs pb;
     uint8_t *dm = s->d_meta.as<uint8_t>();
     pb.qs.qp = (const int8_t *const *)dm;
     pb.qs.mpad = (const int32_t *)(dm + (size_t)s->slots * 8);
     pb.qs.qlen = pb.qs.mpad + s->slots;
     pb.qs.gap = pb.qs.qlen + s->slots;
-    pb.it_q = s->d_items.as<int32_t>();
-    pb.it_g = pb.it_q + n_inter;
-    pb.il_q = pb.it_g + n_inter;
-    pb.il_ids = pb.il_q + n_intra;
-    pb.n_inter = n_inter;
-    pb.n_intra = n_intra;
     pb.scores = s->d_scores.as<int32_t>();
     const int64_t cap = s->ovf_cap;
     pb.ovf_q = s->d_ovf.as<int32_t>();
@@ -1274,24 +1306,48 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
     pb.scr_inter = s->d_scr_inter.as<uint32_t>();
     pb.scr_rows = s->scr_rows;
     pb.scr_intra = s->d_scr_intra.as<int32_t>();
-    Launch L = s->L;
-    // columns per lane of the wave-per-pair work (long list, recompute) from
-    // this pass's longest query; setup sized everything for the widest
-    int64_t max_q = 1;
-    for (const PassWork &w : work) max_q = std::max(max_q, w.qlen);
-    L.Ti = intra_T_for(max_q);
-    L.fused_long = it.fused && n_intra > 0;
-    L.packed_long = !it.fused && it.per_item == 2 * kIntraWaves;
-    L.grid_inter = L.fused_long
-                       ? (int)std::min<int64_t>(n_inter + n_intra, s->grid_fused)
-                       : (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), s->L.grid_inter);
-    L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), s->L.grid_long);
-    TRY(enqueue_pass(db, L, pb, st, nullptr, nullptr, true));
+    for (int x = 0; x < 2; ++x) {
+        if (sub[x].empty()) continue;
+        const Plan &plan = x ? s->plan16 : s->plan;
+        const Launch &base = x ? s->L16 : s->L;
+        Items it;
+        build_work_items(db, plan, sub[x], s->long_ids, x ? false : s->fuse, it);
+        const int64_t n_inter = (int64_t)it.inter_q.size(), n_intra = (int64_t)it.intra_q.size();
+        int32_t *hi = (int32_t *)(s->h_items.as<uint8_t>() + x * s->items_half);
+        int32_t *di = (int32_t *)(s->d_items.as<uint8_t>() + x * s->items_half);
+        std::memcpy(hi, it.inter_q.data(), n_inter * 4);
+        std::memcpy(hi + n_inter, it.inter_g.data(), n_inter * 4);
+        std::memcpy(hi + 2 * n_inter, it.intra_q.data(), n_intra * 4);
+        std::memcpy(hi + 2 * n_inter + n_intra, it.intra_ids.data(), n_intra * it.per_item * 4);
+        const size_t ib = (size_t)(2 * n_inter + n_intra * (1 + it.per_item)) * 4;
+        if (ib) HIPX(hipMemcpyAsync(di, hi, ib, hipMemcpyHostToDevice, st));
+        pb.it_q = di;
+        pb.it_g = pb.it_q + n_inter;
+        pb.il_q = pb.it_g + n_inter;
+        pb.il_ids = pb.il_q + n_intra;
+        pb.n_inter = n_inter;
+        pb.n_intra = n_intra;
+        Launch L = base;
+        // columns per lane of the wave-per-pair work (long list, recompute)
+        // from this sub-pass's longest query; setup sized everything for the
+        // widest
+        int64_t max_q = 1;
+        for (const PassWork &w : sub[x]) max_q = std::max(max_q, w.qlen);
+        L.Ti = intra_T_for(max_q);
+        L.fused_long = it.fused && n_intra > 0;
+        L.packed_long = !it.fused && it.per_item == 2 * kIntraWaves;
+        L.grid_inter = L.fused_long
+                           ? (int)std::min<int64_t>(n_inter + n_intra, s->grid_fused)
+                           : (int)std::min<int64_t>(std::max<int64_t>(n_inter, 1), base.grid_inter);
+        L.grid_long = (int)std::min<int64_t>(std::max<int64_t>(n_intra, 1), base.grid_long);
+        TRY(enqueue_pass(db, L, pb, st, nullptr, nullptr, true));
+    }
     // requests that visited their last position get top-k
     std::vector<int32_t> done_rows;
     for (Request *rp : riders) {
         auto &r = s->active[rp->slot];
         r->passes++;
+        if (riders.size() > 1) r->shared++;
         if (r->remaining == 0) {
             finished.push_back(r);
             done_rows.push_back(r->slot);
@@ -1776,7 +1832,7 @@ int align_pairs(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring 
 }
 }  // namespace
 
-int sw_db_align(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring *sc,
+int sw_db_align(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
                 const int64_t *ids, int32_t n_ids, sw_alignment *out, uint32_t *ops,
                 int64_t ops_cap, int64_t *ops_needed) {
     g_err.clear();
@@ -1842,7 +1898,9 @@ int sw_server_submit(sw_server *srv, const uint8_t *query, int32_t qlen, const s
     r->alpha = sc->alpha;
     r->beta = sc->beta;
     r->k = k;
-    r->bytes = (int64_t)srv->db->R * round_up(qlen, kQPad) + srv->db->n_seqs * 4 + (int64_t)k * 12;
+    // per-request device state: its query profile and its top-k (the score
+    // rows are per slot, allocated when the server starts)
+    r->bytes = (int64_t)srv->db->R * round_up(qlen, kQPad) + (int64_t)k * 12;
     r->t_submit = now_ms();
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) return fail(SW_ESTOPPED, "server stopped");
@@ -1887,6 +1945,7 @@ int sw_server_wait(sw_server *srv, uint64_t ticket, int32_t *top_scores, int64_t
         stats->total_ms = r->t_done - r->t_submit;
         stats->cells = (int64_t)r->query.size() * srv->db->total_res;
         stats->passes = r->passes;
+        stats->shared_passes = r->shared;
     }
     return SW_OK;
 }

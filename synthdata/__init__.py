@@ -198,6 +198,95 @@ def plant_homologs(residues: np.ndarray, offsets: np.ndarray, queries: list[np.n
     return pack_sequences(seqs)
 
 
+def rebuild_db(residues: np.ndarray, offsets: np.ndarray, replace: dict,
+               sort: bool = False) -> tuple[np.ndarray, np.ndarray]:
+    """Database with sequence ``i`` replaced by ``replace[i]`` for each key.
+
+    With ``sort`` the result is stably re-sorted by length (the input is
+    assumed sorted, so only the replaced sequences move); otherwise every
+    sequence keeps its index.  Unchanged sequences are copied as contiguous
+    blocks, so this costs one pass over the residues.
+    """
+    n = len(offsets) - 1
+    lens = np.diff(offsets).astype(np.int64)
+    keys = np.array(sorted(replace), dtype=np.int64)
+    if sort and len(keys):
+        keep = np.ones(n, bool)
+        keep[keys] = False
+        kept = np.flatnonzero(keep)
+        src = np.concatenate([kept, -1 - np.arange(len(keys), dtype=np.int64)])
+        new_lens = np.concatenate([lens[kept],
+                                   np.array([len(replace[int(i)]) for i in keys], np.int64)])
+        perm = np.argsort(new_lens, kind="stable")
+        src, new_lens = src[perm], new_lens[perm]
+    else:
+        src = np.arange(n, dtype=np.int64)
+        new_lens = lens.copy()
+        for j, i in enumerate(keys):
+            new_lens[i] = len(replace[int(i)])
+            src[i] = -1 - j
+    new_off = np.zeros(n + 1, np.int64)
+    np.cumsum(new_lens, out=new_off[1:])
+    out = np.empty(int(new_off[-1]), np.uint8)
+    # Runs of consecutive original indices are copied in one block.
+    brk = np.flatnonzero((src[1:] != src[:-1] + 1) | (src[1:] < 0) | (src[:-1] < 0)) + 1
+    starts = np.concatenate([[0], brk])
+    ends = np.concatenate([brk, [n]])
+    for a, b in zip(starts.tolist(), ends.tolist()):
+        if src[a] < 0:
+            out[new_off[a]:new_off[a + 1]] = replace[int(keys[-1 - src[a]])]
+        else:
+            o = offsets[src[a]]
+            out[new_off[a]:new_off[b]] = residues[o:o + (new_off[b] - new_off[a])]
+    return out, new_off
+
+
+def embed_homologs(residues: np.ndarray, offsets: np.ndarray, queries: list[np.ndarray],
+                   identity: float = 0.85, seed: int = SEED_PLANTED
+                   ) -> tuple[np.ndarray, np.ndarray, list[int]]:
+    """One homolog per query embedded in a random database sequence.
+
+    Sequence ``where[k]`` (distinct, seeded) becomes background flank +
+    ``mutate(queries[k], identity)`` + background flank, with its original
+    length kept (or the homolog's, if longer): a homologous domain inside a
+    longer protein.  Returns (residues, offsets, where).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(offsets) - 1
+    where = [int(x) for x in rng.choice(n, size=len(queries), replace=False)]
+    replace = {}
+    for k, i in enumerate(where):
+        h = mutate(rng, queries[k], identity)
+        total = max(int(offsets[i + 1] - offsets[i]), len(h))
+        left = int(rng.integers(0, total - len(h) + 1))
+        replace[i] = np.concatenate([random_residues(rng, left), h,
+                                     random_residues(rng, total - left - len(h))])
+    res, off = rebuild_db(residues, offsets, replace)
+    return res, off, where
+
+
+# Identities of the members of each planted homolog family.
+FAMILY_IDENTITIES = (0.45, 0.6, 0.75, 0.85, 0.95)
+
+
+def plant_families(residues: np.ndarray, offsets: np.ndarray, queries: list[np.ndarray],
+                   identities=FAMILY_IDENTITIES, sort: bool = False,
+                   seed: int = SEED_PLANTED + 1) -> tuple[np.ndarray, np.ndarray]:
+    """A family of whole-length homologs per query, one per identity.
+
+    Each member replaces a distinct random database sequence.  With ``sort``
+    the database stays length-sorted (members move to their length's place).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = len(offsets) - 1
+    where = rng.choice(n, size=len(queries) * len(identities), replace=False)
+    replace = {}
+    for k, q in enumerate(queries):
+        for f, ident in enumerate(identities):
+            replace[int(where[k * len(identities) + f])] = mutate(rng, q, ident)
+    return rebuild_db(residues, offsets, replace, sort=sort)
+
+
 def poisson_arrivals(rate: float, duration: float, seed: int = SEED_ARRIVALS) -> np.ndarray:
     """Open-loop arrival times (seconds) of a Poisson process."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -237,10 +326,20 @@ class Workload:
     sorted_db: bool = False
     alpha: int = ALPHA_DEFAULT
     beta: int = BETA_DEFAULT
+    # Planted homologs: "" none, "embedded" one per query inside a random
+    # subject (85% identity), "families" whole-length members per query at
+    # FAMILY_IDENTITIES.
+    homologs: str = ""
 
     def db(self):
-        return make_db(self.n_subjects, self.mean_len, self.min_len, self.max_len,
-                       seed=SEED_DB, sort=self.sorted_db, uniform_lengths=self.uniform_lengths)
+        res, off = make_db(self.n_subjects, self.mean_len, self.min_len, self.max_len,
+                           seed=SEED_DB, sort=self.sorted_db,
+                           uniform_lengths=self.uniform_lengths)
+        if self.homologs == "embedded":
+            res, off, _ = embed_homologs(res, off, self.queries())
+        elif self.homologs == "families":
+            res, off = plant_families(res, off, self.queries(), sort=self.sorted_db)
+        return res, off
 
     def queries(self):
         return make_queries(self.query_lengths, seed=SEED_QUERIES)
@@ -258,12 +357,14 @@ WORKLOADS = {
     # 1 query of 144 vs 2,000 subjects (log-normal mean 350, 20..2,000).
     "plain_small": Workload("plain_small", 2000, 350, 20, 2000, [144]),
     # 20 queries (144..5,478) one at a time vs 2M subjects (mean 350, <= 35,000), length-sorted.
+    # Each query has a planted family of 5 homologs (45..95% identity).
     "plain_scale": Workload("plain_scale", 2_000_000, 350, 20, 35000,
-                            list(SCALE_QUERY_LENGTHS), sorted_db=True),
-    # 8 queries 1,000..5,000 vs 20,000 subjects uniform 5,000..35,000.
+                            list(SCALE_QUERY_LENGTHS), sorted_db=True, homologs="families"),
+    # 8 queries 1,000..5,000 vs 20,000 subjects uniform 5,000..35,000; each
+    # query has one 85%-identity homolog embedded in a subject.
     "long_tail": Workload("long_tail", 20000, 20000, 5000, 35000,
                           [int(x) for x in np.rint(np.linspace(1000, 5000, 8))],
-                          uniform_lengths=True),
+                          uniform_lengths=True, homologs="embedded"),
     # 512 queries uniform 50..1,500 vs 500k subjects (mean 350).
     "batched": Workload("batched", 500_000, 350, 20, 35000, _batched_lengths()),
     # Serving DB: 5M subjects (mean 350); queries arrive as a Poisson stream.

@@ -148,8 +148,8 @@ def test_server_tiny_budget_queues_but_completes(swmi, orc):
     M = sd.blosum_style_matrix()
     res, off, db = serve_db(swmi, rng)
     qs = [sd.random_residues(rng, int(L)) for L in rng.integers(30, 300, size=6)]
-    n = len(off) - 1
-    per_request = 21 * 320 + n * 4 + 5 * 12
+    # charged per request: its profile (21 rows x qlen rounded up to 32) and top-k
+    per_request = 21 * 320 + 5 * 12
     try:
         srv = swmi.sw_server_start(db.h, memory_budget=per_request + 100, chunk_groups=8)
         try:
@@ -161,6 +161,80 @@ def test_server_tiny_budget_queues_but_completes(swmi, orc):
             es, ei = oracle_topk(orc, q, res, off, M, 2, 12, 5)
             assert np.array_equal(ts, es) and np.array_equal(ti, ei)
         assert max(st["queue_ms"] for _, _, st in out) > 0
+    finally:
+        db.close()
+
+
+def test_server_mixed_schemes_share_passes(swmi, orc):
+    """Requests with different gap penalties and matrices share passes:
+    alpha up to 28 runs in the fp16 tier, larger alpha (up to past the fp16
+    frame's limit of 53) in the int16 sub-pass of the same passes.  A burst
+    spanning many passes (small chunks) must give every request the same
+    top-k as running alone, and as the oracle, and requests must have shared
+    passes with others."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    M = sd.blosum_style_matrix()
+    M2 = sd.random_matrix(rng, 20, lo=-5, hi=8, symmetric=False)
+    res, off, db = serve_db(swmi, rng)
+    schemes = [(M, 2, 12), (M2, 1, 11), (M, 28, 40), (M2, 29, 29), (M, 40, 60), (M, 60, 80),
+               (M2, 0, 0), (M, 3, 9)]
+    qs = [sd.random_residues(rng, int(L)) for L in rng.integers(40, 900, size=len(schemes))]
+    ks = [5, 12, 7, 3, 10, 4, 9, 6]
+    try:
+        srv = swmi.sw_server_start(db.h, chunk_groups=2, max_active=16)
+        try:
+            alone = []
+            for q, (m, a, b), k in zip(qs, schemes, ks):
+                t = swmi.sw_server_submit(srv, q, m, a, b, k)
+                alone.append(swmi.sw_server_wait(srv, t, k))
+            # the burst: half now, half once the first ones are under way
+            tickets = [swmi.sw_server_submit(srv, q, m, a, b, k)
+                       for q, (m, a, b), k in list(zip(qs, schemes, ks))[:4]]
+            time.sleep(0.003)
+            tickets += [swmi.sw_server_submit(srv, q, m, a, b, k)
+                        for q, (m, a, b), k in list(zip(qs, schemes, ks))[4:]]
+            mixed = [swmi.sw_server_wait(srv, t, k) for t, k in zip(tickets, ks)]
+        finally:
+            swmi.sw_server_stop(srv)
+        shared = [st["shared_passes"] for _, _, st in mixed]
+        print("passes", [st["passes"] for _, _, st in mixed], "shared", shared, flush=True)
+        assert sum(1 for x in shared if x > 0) >= len(qs) - 1, shared
+        for x, (q, (m, a, b), k) in enumerate(zip(qs, schemes, ks)):
+            es, ei = oracle_topk(orc, q, res, off, m, a, b, k)
+            assert np.array_equal(alone[x][0], es) and np.array_equal(alone[x][1], ei), \
+                f"alone {x} alpha {a}"
+            assert np.array_equal(mixed[x][0], es) and np.array_equal(mixed[x][1], ei), \
+                f"mixed {x} alpha {a}"
+    finally:
+        db.close()
+
+
+def test_server_budget_lets_small_requests_pass(swmi, orc):
+    """A long query that does not fit the memory budget beside another waits,
+    while a short one submitted after it is admitted at once."""
+    rng = np.random.Generator(np.random.PCG64(73))
+    M = sd.blosum_style_matrix()
+    res, off, db = serve_db(swmi, rng)
+    qa, qb, qc = (sd.random_residues(rng, L) for L in (2000, 2000, 50))
+    k = 4
+    long_bytes = 21 * 2016 + 12 * k
+    short_bytes = 21 * 64 + 12 * k
+    try:
+        srv = swmi.sw_server_start(db.h, memory_budget=long_bytes + short_bytes + 100,
+                                   chunk_groups=1, max_active=8)
+        try:
+            ta, tb, tc = (swmi.sw_server_submit(srv, q, M, 2, 12, k) for q in (qa, qb, qc))
+            ra, rb, rc = (swmi.sw_server_wait(srv, t, k) for t in (ta, tb, tc))
+        finally:
+            swmi.sw_server_stop(srv)
+        sa, sb, sc_ = ra[2], rb[2], rc[2]
+        print("queue ms", sa["queue_ms"], sb["queue_ms"], sc_["queue_ms"], "A total",
+              sa["total_ms"], flush=True)
+        assert sc_["queue_ms"] < sb["queue_ms"]
+        assert sb["queue_ms"] >= sa["total_ms"] - 5.0   # B waited for A to complete
+        for q, (ts, ti, _) in zip((qa, qb, qc), (ra, rb, rc)):
+            es, ei = oracle_topk(orc, q, res, off, M, 2, 12, k)
+            assert np.array_equal(ts, es) and np.array_equal(ti, ei)
     finally:
         db.close()
 
