@@ -22,6 +22,11 @@ The run takes hours of CPU.  It is resumable: records whose input digests
 match are kept, so an interrupted run continues where it stopped.
 
     python tests/golden/make_full_size.py [--threads N] [--only NAME ...]
+        [--queries I ...] [--out PATH]
+
+--queries limits the run to those query indices; --out writes the records to
+another file (for example on a machine with more cores), whose records
+--merge PATH later copies into this one.
 """
 from __future__ import annotations
 
@@ -71,28 +76,52 @@ def vector_sha256(scores: np.ndarray) -> str:
     return hashlib.sha256(np.ascontiguousarray(scores, dtype="<i4").tobytes()).hexdigest()
 
 
-def load() -> dict:
-    if os.path.exists(OUT):
-        with open(OUT) as f:
+def load(path: str = OUT) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
             return json.load(f)
     return {}
 
 
-def save(doc: dict) -> None:
-    tmp = OUT + ".tmp"
+def save(doc: dict, path: str = OUT) -> None:
+    tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(doc, f, indent=1, sort_keys=True)
         f.write("\n")
-    os.replace(tmp, OUT)
+    os.replace(tmp, path)
+
+
+def merge(src: str) -> None:
+    """Copy the query records of another run's file into OUT, for workloads
+    whose input digests agree."""
+    doc, other = load(), load(src)
+    for name, rec in other.items():
+        if name == "about":
+            continue
+        mine = doc.setdefault(name, {})
+        keys = ("db_sha256", "matrix_sha256", "alpha", "beta", "n_subjects", "residues", "k")
+        if mine and any(mine.get(x) != rec.get(x) for x in keys):
+            raise SystemExit(f"{name}: inputs of {src} differ from {OUT}'s")
+        for x in keys:
+            mine[x] = rec[x]
+        mine.setdefault("queries", {}).update(rec.get("queries", {}))
+        print(f"[golden] merged {len(rec.get('queries', {}))} {name} records", flush=True)
+    save(doc)
 
 
 def main() -> None:
     ap = argparse.ArgumentParser()
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--only", nargs="*", default=None)
+    ap.add_argument("--queries", nargs="*", type=int, default=None)
+    ap.add_argument("--out", default=OUT)
+    ap.add_argument("--merge", default=None)
     args = ap.parse_args()
+    if args.merge:
+        merge(args.merge)
+        return
     orc = oracle.load()
-    doc = load()
+    doc = load(args.out)
     doc["about"] = ("Oracle score-vector digests and top-10 at full size; written by "
                     "tests/golden/make_full_size.py, which calls only oracle/.")
     for name in ORDER:
@@ -114,6 +143,8 @@ def main() -> None:
         print(f"[golden] {name}: {len(qs)} queries, {len(off) - 1} subjects "
               f"(inputs in {time.time() - t0:.1f}s)", flush=True)
         for i, q in zip(idx, qs):
+            if args.queries is not None and i not in args.queries:
+                continue
             key = str(i)
             q_sha = sd.sha256(q)
             if entries.get(key, {}).get("query_sha256") == q_sha:
@@ -127,11 +158,11 @@ def main() -> None:
                 "top_scores": ts.tolist(), "top_idx": ti.tolist(),
                 "max": int(scores.max()), "n_ge_1848": int((scores >= 1848).sum()),
             }
-            save(doc)
+            save(doc, args.out)
             dt = time.time() - t1
             print(f"[golden] {name} q{i} ({len(q)}): {len(q) * int(off[-1]) / dt / 1e9:.2f} "
                   f"GCUPS, {dt:.0f}s, max {int(scores.max())}", flush=True)
-    save(doc)
+    save(doc, args.out)
 
 
 if __name__ == "__main__":
