@@ -14,6 +14,9 @@ Also measured in the same run, as sub-objects of the JSON line:
            replayed from a captured HIP graph (with the autotuner run on the
            batch's query lengths first), and
            the same 512 queries as 512 plain top-k searches of that database;
+  streamed: the 20 queries as one batch through an on-disk index streamed
+           chunk by chunk under a 1 GiB device budget, against the same batch
+           with the database resident;
   served:  Poisson arrivals against a resident 5M-subject database
            (continuous batching), p50/p99 latency and sustained GCUPS, at
            50 queries/s over a short window (labelled with its window and
@@ -275,6 +278,48 @@ def run_plain(args, swmi, sd, torch):
     return out, (w, res, off, queries, M)
 
 
+def run_streamed(args, swmi, torch, w, res, off, queries, M):
+    """The same queries as one batch through an on-disk index whose chunks
+    (128 M residues) stream through two device slots under a 1 GiB memory
+    budget, against the same batch on the whole database resident in HBM."""
+    cells = sum(len(q) for q in queries) * int(len(res))
+    out = {"queries": len(queries), "chunk_residues": 128 << 20, "memory_budget": 1 << 30}
+    db = swmi.Database(res, off, 20, device=0)
+    try:
+        swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, args.k)   # warmup + capture
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        swmi.sw_db_search_batch(db.h, queries, M, w.alpha, w.beta, args.k)
+        dt_res = time.perf_counter() - t
+    finally:
+        db.close()
+    log(f"[bench] streamed: resident batch {cells / dt_res / 1e9:.1f} GCUPS; writing the index")
+    with tempfile.TemporaryDirectory() as td:
+        path = os.path.join(td, "db.swx")
+        t = time.perf_counter()
+        swmi.sw_index_write(path, res, off, 20, 128 << 20)
+        out["index_write_s"] = round(time.perf_counter() - t, 2)
+        out["index_bytes"] = os.path.getsize(path)
+        ix = swmi.Index(path, device=0, memory_budget=1 << 30)
+        try:
+            ix.search_batch(queries, M, w.alpha, w.beta, args.k)   # warmup
+            t = time.perf_counter()
+            ix.search_batch(queries, M, w.alpha, w.beta, args.k)
+            dt = time.perf_counter() - t
+            st = ix.stats()
+        finally:
+            ix.close()
+    g, g_res = cells / dt / 1e9, cells / dt_res / 1e9
+    log(f"[bench] streamed: {g:.1f} GCUPS over {st['chunks']} chunks")
+    out.update({"chunks": st["chunks"], "resident": bool(st["resident"]),
+                "bytes_loaded": st["bytes_loaded"], "load_ms": round(st["load_ms"], 1),
+                "search_ms": round(st["search_ms"], 1), "kernel_ms": round(st["kernel_ms"], 1),
+                "ms": round(dt * 1e3, 1), "gcups": round(g, 2),
+                "resident_batch_ms": round(dt_res * 1e3, 1), "resident_batch_gcups": round(g_res, 2),
+                "vs_resident": round(g / g_res, 4)})
+    return out
+
+
 def run_align(args, swmi, db, w, res, off, queries, M):
     """Alignment with traceback (sw_db_align) of every query's top-k hits:
     the hits come from untimed searches; the timed region is the align calls
@@ -397,8 +442,10 @@ def serve_phase(swmi, srv, M, alpha, beta, queries, arrivals, total_res, collect
     for _ in pool:
         tickets.put(None)
     while any(th.is_alive() for th in pool):
+        # one progress line every 10 s however many collectors are still waiting
+        t_next = time.perf_counter() + 10.0
         for th in pool:
-            th.join(timeout=10.0)
+            th.join(timeout=max(0.0, t_next - time.perf_counter()))
         log(f"[bench] serving: draining, {len(done_at)} of {len(submitted_at)} done "
             f"at {time.perf_counter() - t0:.0f}s")
     span = time.perf_counter() - t0
@@ -476,6 +523,7 @@ def main():
     ap.add_argument("--batched-steps", type=int, default=1)
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-align", action="store_true")
+    ap.add_argument("--no-streamed", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--only-served", action="store_true",
                     help="run only the served workload's 50/s phase and print its record")
@@ -510,6 +558,8 @@ def main():
                           "data": "synthetic", "served": rec}), flush=True)
         return
     out, (w, res, off, queries, M) = run_plain(args, swmi, sd, torch)
+    if not args.no_streamed and args.workload == "plain_scale":
+        out["streamed"] = run_streamed(args, swmi, torch, w, res, off, queries, M)
     if not args.no_batched and args.workload == "plain_scale":
         out["batched"] = run_batched(args, swmi, sd, torch)
     if not args.no_served and args.workload == "plain_scale":
