@@ -320,6 +320,45 @@ def run_streamed(args, swmi, torch, w, res, off, queries, M):
     return out
 
 
+def run_profile_ab(args, swmi, sd, torch):
+    """A/B of the lane-per-subject kernel's two profiles on plain_scale's 20
+    query lengths: the pair profile (the default) against the score profile
+    (section III.B.3), same plan (fp16, strip 32, 4 waves), every subject
+    lane-per-subject (no long list, so each launch holds the same work), best
+    of three timed launches per query after one warm-up."""
+    w = sd.WORKLOADS["plain_scale"]
+    res, off = w.db()
+    queries = w.queries()
+    M = w.matrix()
+    db = swmi.Database(res, off, 20, long_threshold=-1, device=0)
+    sptr = torch.cuda.current_stream().cuda_stream
+    rows = []
+    try:
+        for q in queries:
+            row = {"qlen": len(q)}
+            for name, prof in (("pair", 0), ("score", 1)):
+                db.set_opts(tier=1, strip=32, waves=4, profile=prof)
+                best = 1e30
+                for rep in range(4):
+                    swmi.sw_db_topk(db.h, q, M, w.alpha, w.beta, 10, stream=sptr)
+                    st = db.stats()
+                    assert st["profile"] == prof
+                    if rep:
+                        best = min(best, st["inter_ms"])
+                row[f"{name}_ms"] = round(best, 3)
+                row[f"{name}_gcups"] = round(st["inter_cells"] / (best * 1e6), 1)
+            row["score_vs_pair"] = round(row["score_gcups"] / row["pair_gcups"], 4)
+            rows.append(row)
+            log(f"[bench] profile A/B |Q|={len(q)}: pair {row['pair_gcups']} score "
+                f"{row['score_gcups']} GCUPS")
+    finally:
+        db.close()
+    tot_p = sum(r["pair_ms"] for r in rows)
+    tot_s = sum(r["score_ms"] for r in rows)
+    return {"workload": w.name, "plan": "fp16, strip 32, 4 waves, no long list",
+            "rows": rows, "score_vs_pair_total_time": round(tot_p / tot_s, 4)}
+
+
 def run_align(args, swmi, db, w, res, off, queries, M):
     """Alignment with traceback (sw_db_align) of every query's top-k hits:
     the hits come from untimed searches; the timed region is the align calls
@@ -524,6 +563,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--profile-ab", action="store_true",
+                    help="only the pair- vs score-profile A/B on plain_scale's query lengths")
     ap.add_argument("--serve-seconds", type=float, default=4.0)
     ap.add_argument("--only-served", action="store_true",
                     help="run only the served workload's 50/s phase and print its record")
@@ -551,6 +592,11 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         log(f"[bench] copied {n} bytes device to device, 3 times")
+        return
+    if args.profile_ab:
+        rec = run_profile_ab(args, swmi, sd, torch)
+        print(json.dumps({"metric": "lane-per-subject kernel GCUPS, pair vs score profile",
+                          "unit": "GCUPS", "data": "synthetic", "profile_ab": rec}), flush=True)
         return
     if args.only_served:
         rec = run_served(args, swmi, sd, torch)

@@ -90,8 +90,20 @@ typedef struct sw_search_opts {
     int32_t graph;          /* sw_db_search_batch: 0 = capture the device work of a batch shape in
                                a HIP graph and replay it on later calls of that shape, -1 = launch
                                eagerly every time */
-    int32_t reserved[3];
+    int32_t profile;        /* substitution scores of the lane-per-subject kernel: SW_PROFILE_PAIR
+                               (0) or SW_PROFILE_SCORE; the planner never picks the latter itself */
+    int32_t reserved[2];
 } sw_search_opts;
+
+/* Profiles of the lane-per-subject kernel (sw_search_opts.profile). */
+#define SW_PROFILE_PAIR  0   /* query profile per strip, read at each lane's subject-residue pair
+                                (section III.B.2; two subjects per 32-bit lane) */
+#define SW_PROFILE_SCORE 1   /* score profile (section III.B.3): each lane's row of its subject
+                                residues' scores against every query letter, read at the query
+                                letter.  Taken only with the fp16 tier, strip 32, 4 waves and an
+                                alphabet of at most 23 letters (searches through sw_db_search,
+                                sw_db_search_dev, sw_db_topk and sw_db_search_batch); otherwise
+                                the pair profile runs.  sw_stats.profile reports which ran. */
 
 /* Statistics of the last search call on a database handle. */
 typedef struct sw_stats {
@@ -114,6 +126,8 @@ typedef struct sw_stats {
                                  (-1 when the work ran as a graph) */
     double  long_ms;          /* device time of the wave-per-pair kernel when it ran alone
                                  (no lane-per-subject work in the call); -1 otherwise */
+    int32_t profile;          /* SW_PROFILE_* of the lane-per-subject kernel */
+    int32_t reserved0;
 } sw_stats;
 
 /* Open a database (section III, stage ii: sequences are sorted by length and
@@ -270,6 +284,65 @@ int sw_server_wait(sw_server *srv, uint64_t ticket, int32_t *top_scores, int64_t
  * blocked in sw_server_wait return before this call does.  No sw_server_* call
  * may use the handle afterwards.  NULL is ignored. */
 void sw_server_stop(sw_server *srv);
+
+/* ---- databases larger than device memory ----
+ * Section III's workflow: the database is sorted and indexed offline, and the
+ * search loads it chunk by chunk.  The index file holds the subjects sorted by
+ * length and cut into chunks of about chunk_residues residues, each stored in
+ * the packed device layout of sw_db_open (its subjects in ascending database
+ * order).  A search keeps the whole index on the device when it fits the
+ * memory budget; otherwise it streams the chunks through two device slots,
+ * loading chunk c+1 (host thread, copies on the slot's own stream) while
+ * chunk c is searched.  Results equal sw_db_search_batch on the same database
+ * opened whole: the per-chunk top-k lists merge by (score desc, database index
+ * asc). */
+typedef struct sw_index sw_index;
+
+typedef struct sw_index_opts {
+    int32_t device;          /* HIP device ordinal; <= 0 means device 0 */
+    int32_t reserved0;
+    int64_t memory_budget;   /* device bytes the database copies may take (search workspaces
+                                come on top); 0 = half of the device's free memory.  The index
+                                stays resident when all chunks fit, else it is streamed, which
+                                needs two of its largest chunk to fit (else SW_ENOMEM). */
+    int32_t reserved[4];
+} sw_index_opts;
+
+typedef struct sw_index_stats {
+    int64_t chunks;          /* chunks in the index */
+    int32_t resident;        /* 1 if every chunk stays on the device */
+    int32_t reserved0;
+    int64_t bytes_loaded;    /* chunk bytes copied to the device by the last search */
+    int64_t cells;           /* sum |Q| * sum |S| */
+    double  load_ms;         /* host-thread time loading chunks (overlaps the searches) */
+    double  search_ms;       /* wall time of the per-chunk searches */
+    double  kernel_ms;       /* device time of their kernels */
+    double  total_ms;        /* wall time of the whole call */
+} sw_index_stats;
+
+/* Write an index of the database (residues/offsets as in sw_db_open) to path.
+ * chunk_residues >= 1: residues per chunk (a chunk holds at least one subject).
+ * Needs no GPU: chunks are packed for 256 compute units (MI355X). */
+int sw_index_write(const char *path, const uint8_t *residues, const int64_t *offsets,
+                   int64_t n_seqs, int32_t alphabet, int64_t chunk_residues);
+
+/* Map an index file and prepare its device slots (opts may be NULL). */
+int sw_index_open(const char *path, const sw_index_opts *opts, sw_index **out);
+
+/* Release an index (NULL is ignored). */
+void sw_index_close(sw_index *ix);
+
+/* Number of sequences in the index (-1 for NULL). */
+int64_t sw_index_size(const sw_index *ix);
+
+/* Statistics of the last search on this index. */
+int sw_index_last_stats(sw_index *ix, sw_index_stats *out);
+
+/* Many queries against the whole index; arguments and results as
+ * sw_db_search_batch (host memory, database order), synchronous. */
+int sw_index_search_batch(sw_index *ix, int32_t nq, const uint8_t *q_res, const int64_t *q_off,
+                          const sw_scoring *sc, int32_t k, int32_t *top_scores, int64_t *top_idx,
+                          int32_t *all_scores);
 
 /* Message for the last failed call on this thread ("" if none). */
 const char *sw_last_error(void);

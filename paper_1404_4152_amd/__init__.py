@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("SWMI_LIB") or os.path.join(HERE, "libswmi.so")
 
 SW_OK, SW_EINVAL, SW_ENOMEM, SW_EDEVICE, SW_EBUSY, SW_ENOTFOUND, SW_ESTOPPED = 0, -1, -2, -3, -4, -5, -6
 SW_TIER_AUTO, SW_TIER_F16X2, SW_TIER_I16X2 = 0, 1, 2
+SW_PROFILE_PAIR, SW_PROFILE_SCORE = 0, 1
 SW_MAX_K = 4096
 SW_MAX_ALPHABET = 32
 
@@ -41,7 +42,7 @@ class sw_db_opts(ctypes.Structure):
 class sw_search_opts(ctypes.Structure):
     _fields_ = [("tier", ctypes.c_int32), ("strip", ctypes.c_int32), ("waves", ctypes.c_int32),
                 ("sat_threshold", ctypes.c_int32), ("graph", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class sw_stats(ctypes.Structure):
@@ -51,7 +52,8 @@ class sw_stats(ctypes.Structure):
                 ("inter_ms", ctypes.c_double), ("tier", ctypes.c_int32), ("strip", ctypes.c_int32),
                 ("waves", ctypes.c_int32), ("graphed", ctypes.c_int32),
                 ("fused_long", ctypes.c_int32), ("recompute_ms", ctypes.c_double),
-                ("long_ms", ctypes.c_double)]
+                ("long_ms", ctypes.c_double), ("profile", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32)]
 
 
 class sw_alignment(ctypes.Structure):
@@ -70,6 +72,19 @@ class sw_req_stats(ctypes.Structure):
     _fields_ = [("queue_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("cells", ctypes.c_int64), ("passes", ctypes.c_int32),
                 ("shared_passes", ctypes.c_int32)]
+
+
+class sw_index_opts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("reserved", ctypes.c_int32 * 4)]
+
+
+class sw_index_stats(ctypes.Structure):
+    _fields_ = [("chunks", ctypes.c_int64), ("resident", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("bytes_loaded", ctypes.c_int64),
+                ("cells", ctypes.c_int64), ("load_ms", ctypes.c_double),
+                ("search_ms", ctypes.c_double), ("kernel_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
 
 
 _P = ctypes.POINTER
@@ -97,6 +112,14 @@ SIGNATURES = {
                                         _P(ctypes.c_uint64)]),
     "sw_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, _i32p, _i64p, _P(sw_req_stats)]),
     "sw_server_stop": (None, [_vp]),
+    "sw_index_write": (ctypes.c_int, [ctypes.c_char_p, _u8p, _i64p, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_int64]),
+    "sw_index_open": (ctypes.c_int, [ctypes.c_char_p, _P(sw_index_opts), _P(_vp)]),
+    "sw_index_close": (None, [_vp]),
+    "sw_index_size": (ctypes.c_int64, [_vp]),
+    "sw_index_last_stats": (ctypes.c_int, [_vp, _P(sw_index_stats)]),
+    "sw_index_search_batch": (ctypes.c_int, [_vp, ctypes.c_int32, _u8p, _i64p, _P(sw_scoring),
+                                             ctypes.c_int32, _i32p, _i64p, _i32p]),
     "sw_last_error": (ctypes.c_char_p, []),
     "sw_version": (ctypes.c_char_p, []),
 }
@@ -179,17 +202,17 @@ def sw_db_size(h) -> int:
     return int(lib().sw_db_size(h))
 
 
-def sw_db_set_opts(h, tier=0, strip=0, waves=0, sat_threshold=0, graph=0, reset=False):
+def sw_db_set_opts(h, tier=0, strip=0, waves=0, sat_threshold=0, graph=0, profile=0, reset=False):
     if reset:
         return _check(lib().sw_db_set_opts(h, None))
-    o = sw_search_opts(tier, strip, waves, sat_threshold, graph)
+    o = sw_search_opts(tier, strip, waves, sat_threshold, graph, profile)
     return _check(lib().sw_db_set_opts(h, ctypes.byref(o)))
 
 
 def sw_db_last_stats(h) -> dict:
     s = sw_stats()
     _check(lib().sw_db_last_stats(h, ctypes.byref(s)))
-    return {f: getattr(s, f) for f, _ in sw_stats._fields_ if f != "reserved"}
+    return {f: getattr(s, f) for f, _ in sw_stats._fields_ if not f.startswith("reserved")}
 
 
 def sw_db_search(h, query, matrix, alpha, beta, stream=None):
@@ -311,6 +334,79 @@ def sw_server_wait(srv, ticket, k):
 
 def sw_server_stop(srv):
     lib().sw_server_stop(srv)
+
+
+def sw_index_write(path, residues, offsets, alphabet, chunk_residues):
+    res = _u8(residues)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    return _check(lib().sw_index_write(os.fsencode(path), _ptr(res, ctypes.c_uint8),
+                                       _ptr(off, ctypes.c_int64), len(off) - 1, int(alphabet),
+                                       int(chunk_residues)))
+
+
+def sw_index_open(path, device=0, memory_budget=0):
+    o = sw_index_opts(device, 0, int(memory_budget))
+    h = _vp()
+    _check(lib().sw_index_open(os.fsencode(path), ctypes.byref(o), ctypes.byref(h)))
+    return h
+
+
+def sw_index_close(h):
+    lib().sw_index_close(h)
+
+
+def sw_index_size(h) -> int:
+    return int(lib().sw_index_size(h))
+
+
+def sw_index_last_stats(h) -> dict:
+    st = sw_index_stats()
+    _check(lib().sw_index_last_stats(h, ctypes.byref(st)))
+    return {f: getattr(st, f) for f, _ in sw_index_stats._fields_ if not f.startswith("reserved")}
+
+
+def sw_index_search_batch(h, queries, matrix, alpha, beta, k, all_scores=False):
+    res, off = pack_queries(queries)
+    res = _u8(res)
+    nq = len(queries)
+    sc, keep = make_scoring(matrix, alpha, beta)
+    ts = np.zeros(nq * k, np.int32)
+    ti = np.zeros(nq * k, np.int64)
+    n = sw_index_size(h)
+    al = np.zeros(max(nq * n, 1), np.int32) if all_scores else None
+    _check(lib().sw_index_search_batch(h, nq, _ptr(res, ctypes.c_uint8), _ptr(off, ctypes.c_int64),
+                                       ctypes.byref(sc), int(k), _ptr(ts, ctypes.c_int32),
+                                       _ptr(ti, ctypes.c_int64),
+                                       _ptr(al, ctypes.c_int32) if al is not None else None))
+    out = (ts.reshape(nq, k), ti.reshape(nq, k))
+    if all_scores:
+        out = out + (al[:nq * n].reshape(nq, n),)
+    return out
+
+
+class Index:
+    """An on-disk index searched resident or streamed (closed on ``close``/GC)."""
+
+    def __init__(self, path, device=0, memory_budget=0):
+        self.h = sw_index_open(path, device, memory_budget)
+        self.n = sw_index_size(self.h)
+
+    def close(self):
+        if self.h:
+            sw_index_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def search_batch(self, queries, matrix, alpha, beta, k, all_scores=False):
+        return sw_index_search_batch(self.h, queries, matrix, alpha, beta, k, all_scores)
+
+    def stats(self):
+        return sw_index_last_stats(self.h)
 
 
 class Database:

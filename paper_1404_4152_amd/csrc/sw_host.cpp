@@ -19,7 +19,11 @@
 // Alignment with traceback (sw_db_align): the optimal local alignments of one
 // query against chosen database sequences, computed on the GPU with one
 // direction byte per cell and a walk back.
+#include <fcntl.h>
 #include <hip/hip_runtime.h>
+#include <sys/mman.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <atomic>
@@ -140,6 +144,7 @@ struct Plan {
     int strip = 32;
     int waves = 4;
     int thr = kThrF16;
+    int profile = SW_PROFILE_PAIR;
 };
 
 constexpr int kIntraWaves = 4;   // waves per workgroup of the wave-per-pair kernel (long list)
@@ -198,8 +203,26 @@ struct Launch {
 
 }  // namespace
 
+// Host side of a database's device layout (pack_db).
+struct Packed {
+    int64_t n_seqs = 0, total_res = 0, max_len = 0;
+    int32_t alphabet = 0;
+    std::vector<int64_t> len;            // caller order
+    std::vector<int32_t> long_ids;       // longest first
+    int64_t long_res = 0, long_threshold = 0;
+    bool fixed_cut = false;
+    int32_t n_groups = 0, max_rows = 0;
+    std::vector<int32_t> grp_rows;       // ascending
+    int64_t inter_res = 0, inter_padded_rows = 0;
+    std::vector<int32_t> grp_ids;        // n_groups x 128, -1 = empty slot
+    std::vector<int64_t> grp_res_prefix; // n_groups + 1
+    std::vector<int64_t> gbase;          // first code of each group
+    std::vector<uint16_t> codes;         // pair codes
+};
+
 struct sw_db {
     int device = 0;
+    std::string arch;
     hipStream_t stream = nullptr;
     // Second stream for the long list, forked from and joined to the search's
     // stream so the wave-per-pair kernel overlaps the lane-per-subject kernel.
@@ -284,6 +307,11 @@ Plan plan_for(const sw_db *db, int64_t max_qlen, int alpha) {
     // The pair profile must fit in LDS.
     while (p.strip > 16 && inter_lds_bytes(db->R, p.strip) > 150 * 1024) p.strip /= 2;
     p.thr = p.tier == TIER_I16X2 ? kThrI16 : kThrF16;
+    // the score-profile kernel exists for one plan only
+    p.profile = db->opts.profile == SW_PROFILE_SCORE && p.tier == TIER_F16X2 && p.strip == 32 &&
+                        p.waves == 4 && db->alphabet <= kSpMaxAlphabet
+                    ? SW_PROFILE_SCORE
+                    : SW_PROFILE_PAIR;
     if (db->opts.sat_threshold > 0 && db->opts.sat_threshold < p.thr) p.thr = db->opts.sat_threshold;
     return p;
 }
@@ -310,16 +338,16 @@ void write_profile(int8_t *dst, const uint8_t *q, int64_t qlen, int32_t mpad, co
 // queries the share is large and every group stays lane-per-subject.
 // Returns the number of leading groups (a multiple of the block size) to run
 // lane-per-subject, and appends the routed subjects to `long_ids`.
-int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> &mpad,
-                  int resident_waves, std::vector<int32_t> &long_ids) {
-    long_ids = db->long_ids;
+// The cut alone (allocates nothing): the number of leading groups.
+int64_t route_cut_groups(const sw_db *db, const Plan &plan, const int32_t *mpad, int64_t nq,
+                         int resident_waves) {
     const int W = plan.waves;
     if (db->n_groups == 0) return 0;
     int64_t g_cut = db->n_groups;
     if (!db->fixed_cut) {
         double strips = 0, max_strips = 1;
-        for (int32_t m : mpad) {
-            const double ms = (m + plan.strip - 1) / plan.strip;
+        for (int64_t x = 0; x < nq; ++x) {
+            const double ms = (mpad[x] + plan.strip - 1) / plan.strip;
             strips += ms;
             max_strips = std::max<double>(max_strips, ms);
         }
@@ -331,6 +359,15 @@ int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> 
                 db->grp_rows.begin();
         if (g_cut < db->n_groups) g_cut = g_cut / W * W;
     }
+    return g_cut;
+}
+
+int64_t route_cut(const sw_db *db, const Plan &plan, const std::vector<int32_t> &mpad,
+                  int resident_waves, std::vector<int32_t> &long_ids) {
+    long_ids = db->long_ids;
+    if (db->n_groups == 0) return 0;
+    const int64_t g_cut =
+        route_cut_groups(db, plan, mpad.data(), (int64_t)mpad.size(), resident_waves);
     std::vector<int32_t> routed;
     for (int64_t g = db->n_groups - 1; g >= g_cut; --g)
         for (int x = kGroup - 1; x >= 0; --x) {
@@ -468,7 +505,9 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
     L.fused_long = fused && n_intra > 0;
     L.grid_inter = (int)std::min<int64_t>(
         L.fused_long ? n_inter + n_intra : n_inter,
-        inter_max_grid(db->R, plan.tier, plan.strip, plan.waves, L.fused_long ? L.Ti : 0));
+        plan.profile == SW_PROFILE_SCORE
+            ? inter_sp_max_grid(db->R, plan.waves)
+            : inter_max_grid(db->R, plan.tier, plan.strip, plan.waves, L.fused_long ? L.Ti : 0));
     // either wave-per-pair kernel (int32 or packed: the same profile and feed
     // rings per workgroup)
     const int per_cu =
@@ -480,7 +519,7 @@ Launch launch_config(const sw_db *db, const Plan &plan, int64_t max_qlen, int64_
 }
 
 bool fuse_ok(const sw_db *db, const Plan &plan, int ti) {
-    return plan.tier == TIER_F16X2 && plan.strip == kFuseStrip &&
+    return plan.profile == SW_PROFILE_PAIR && plan.tier == TIER_F16X2 && plan.strip == kFuseStrip &&
            (plan.waves == 4 || plan.waves == 6 || plan.waves == 8) &&
            wpp_lds_bytes(db->R, ti, plan.waves) <= inter_lds_bytes(db->R, plan.strip);
 }
@@ -577,8 +616,13 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
         fl.item_q = b.il_q;
         fl.item_ids = b.il_ids;
         fl.n_items = (int32_t)b.n_intra;
-        HIPX(launch_inter(a, fused ? &fl : nullptr, L.Ti, L.plan.tier, L.plan.strip, L.plan.waves,
-                          L.grid_inter, st));
+        if (L.plan.profile == SW_PROFILE_SCORE) {
+            if (!b.qs.qc) return fail(SW_EINVAL, "internal: score profile without query codes");
+            HIPX(launch_inter_sp(a, L.plan.strip, L.plan.waves, L.grid_inter, st));
+        } else {
+            HIPX(launch_inter(a, fused ? &fl : nullptr, L.Ti, L.plan.tier, L.plan.strip, L.plan.waves,
+                              L.grid_inter, st));
+        }
     }
     if (ev_b) HIPX(hipEventRecord(ev_b, st));
     const bool packed_long = L.packed_long;
@@ -622,9 +666,11 @@ TopkWork topk_work(void *base, int32_t nq, int32_t k) {
 // Layout of the per-call staging area (host pinned -> device, one copy).
 struct StageLayout {
     size_t prof = 0, ptrs = 0, mpad = 0, qlen = 0, gap = 0, items = 0, total = 0;
+    size_t qc = 0, qcd = 0;   // score profile: pointer per query, then matrix + codes blocks
 };
 
-StageLayout stage_layout(int32_t nq, int64_t prof_bytes, const Items &it) {
+// code_bytes > 0: the score-profile kernel's per-query blocks (after the profiles).
+StageLayout stage_layout(int32_t nq, int64_t prof_bytes, const Items &it, int64_t code_bytes = 0) {
     // Fixed-size parts first: their offsets depend only on nq and the item
     // counts, which a captured graph's key pins; the profiles go last.
     StageLayout s;
@@ -639,8 +685,12 @@ StageLayout stage_layout(int32_t nq, int64_t prof_bytes, const Items &it) {
     o += (size_t)round_up((int64_t)nq * 8, 256);
     s.items = o;
     o += (size_t)round_up((int64_t)(it.inter_q.size() * 2 + it.intra_q.size() * (1 + it.per_item)) * 4, 256);
+    s.qc = o;
+    if (code_bytes > 0) o += (size_t)round_up((int64_t)nq * 8, 256);
     s.prof = o;
     o += (size_t)round_up(prof_bytes, 256);
+    s.qcd = o;
+    o += (size_t)round_up(code_bytes, 256);
     s.total = o;
     return s;
 }
@@ -682,7 +732,9 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     std::vector<int32_t> slots(nq);
     std::iota(slots.begin(), slots.end(), 0);
     std::vector<int32_t> long_ids;
-    const int resident = inter_max_grid(db->R, plan.tier, plan.strip, plan.waves) * plan.waves;
+    const int resident = (plan.profile == SW_PROFILE_SCORE
+                              ? inter_sp_max_grid(db->R, plan.waves)
+                              : inter_max_grid(db->R, plan.tier, plan.strip, plan.waves)) * plan.waves;
     const int64_t g_cut = route_cut(db, plan, mpad, resident, long_ids);
     Items it;
     const int64_t nblk = (g_cut + plan.waves - 1) / plan.waves;
@@ -697,7 +749,16 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     for (int32_t id : long_ids) long_res += db->len[id];
 
     // ---- device workspaces ----
-    const StageLayout sl = stage_layout(nq, prof_bytes, it);
+    // score profile: per query the A x A matrix, then its codes padded to mpad with the pad letter
+    const int64_t A = db->alphabet;
+    std::vector<int64_t> qcoff(nq, 0);
+    int64_t code_bytes = 0;
+    if (plan.profile == SW_PROFILE_SCORE)
+        for (int32_t q = 0; q < nq; ++q) {
+            qcoff[q] = code_bytes;
+            code_bytes += round_up(A * A + mpad[q], 16);
+        }
+    const StageLayout sl = stage_layout(nq, prof_bytes, it, code_bytes);
     TRY(db->w_stage.reserve(sl.total));
     TRY(db->w_scores.reserve((size_t)nq * n * 4 + 4));
     TRY(db->w_counters.reserve(256));
@@ -733,6 +794,16 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
             gp[2 * q] = sc->alpha;
             gp[2 * q + 1] = sc->beta;
         }
+        if (code_bytes > 0) {
+            const uint8_t **qc = (const uint8_t **)(hs + sl.qc);
+            for (int32_t q = 0; q < nq; ++q) {
+                uint8_t *blk = hs + sl.qcd + qcoff[q];
+                qc[q] = ds + sl.qcd + qcoff[q];
+                std::memcpy(blk, sc->matrix, (size_t)(A * A));
+                std::memcpy(blk + A * A, q_res + q_off[q], (size_t)qlen[q]);
+                std::memset(blk + A * A + qlen[q], (int)A, (size_t)(mpad[q] - qlen[q]));
+            }
+        }
         int32_t *p = (int32_t *)(hs + sl.items);
         std::memcpy(p, it.inter_q.data(), n_inter * 4);
         std::memcpy(p + n_inter, it.inter_g.data(), n_inter * 4);
@@ -746,6 +817,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     pb.qs.mpad = (const int32_t *)(ds + sl.mpad);
     pb.qs.qlen = (const int32_t *)(ds + sl.qlen);
     pb.qs.gap = (const int32_t *)(ds + sl.gap);
+    pb.qs.qc = code_bytes > 0 ? (const uint8_t *const *)(ds + sl.qc) : nullptr;
     pb.it_q = (const int32_t *)(ds + sl.items);
     pb.it_g = pb.it_q + n_inter;
     pb.il_q = pb.it_g + n_inter;
@@ -778,8 +850,8 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
         // Every kernel argument of the pass is fixed by this key; what changes
         // between calls of one shape (profiles, items) arrives by the staging copy.
         char key[512];
-        snprintf(key, sizeof key, "%d|%d|%d|%d|%d|%d|%d|%lld|%lld|%d|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%p",
-                 rows_alloc, nq, k, plan.tier, plan.strip, plan.waves, plan.thr, (long long)n_inter,
+        snprintf(key, sizeof key, "%d|%d|%d|%d|%d|%d|%d|%d|%lld|%lld|%d|%d|%d|%d|%p|%p|%p|%p|%p|%p|%p|%p",
+                 rows_alloc, nq, k, plan.tier, plan.strip, plan.waves, plan.thr, plan.profile, (long long)n_inter,
                  (long long)n_intra, L.Ti, L.grid_inter, L.grid_long, L.grid_ovf, (void *)ds,
                  (void *)pb.scores, (void *)pb.ovf_q, (void *)pb.counters, (void *)pb.scr_inter,
                  (void *)pb.scr_intra, db->w_topk.p, (void *)d_ti);
@@ -860,6 +932,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     s.waves = plan.waves;
     s.graphed = graphed ? 1 : 0;
     s.fused_long = L.fused_long ? 1 : 0;
+    s.profile = plan.profile;
     return SW_OK;
 }
 
@@ -1082,6 +1155,7 @@ int server_setup(sw_server *s) {
     sw_db *db = s->db;
     HIPX(hipSetDevice(db->device));
     s->plan = plan_for(db, 512, 0);
+    s->plan.profile = SW_PROFILE_PAIR;   // passes carry no query codes
     const int W = s->plan.waves;
     // A request whose alpha would lower the fp16 ceiling past kFrameMaxAlpha
     // runs in an int16 sub-pass of its own (the planner's choice for a plain
@@ -1444,6 +1518,277 @@ void server_loop(sw_server *s) {
 }  // namespace
 
 // ===========================================================================
+// Database layout (section III, stage ii and the offline index): validation,
+// the host-side packing into length-sorted groups, and the upload.
+// ===========================================================================
+namespace {
+
+int validate_db(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, int32_t alphabet) {
+    if (n_seqs < 0) return fail(SW_EINVAL, "n_seqs < 0");
+    if (n_seqs > INT32_MAX - 1) return fail(SW_EINVAL, "too many sequences");
+    if (alphabet < 1 || alphabet > SW_MAX_ALPHABET)
+        return fail(SW_EINVAL, "alphabet %d not in 1..%d", alphabet, SW_MAX_ALPHABET);
+    if (!offsets) return fail(SW_EINVAL, "offsets is NULL");
+    if (offsets[0] != 0) return fail(SW_EINVAL, "offsets[0] != 0");
+    for (int64_t i = 0; i < n_seqs; ++i) {
+        const int64_t L = offsets[i + 1] - offsets[i];
+        if (L < 0) return fail(SW_EINVAL, "offsets decrease at %lld", (long long)i);
+        if (L > SW_MAX_LEN) return fail(SW_EINVAL, "sequence %lld longer than 2^24", (long long)i);
+    }
+    const int64_t total = offsets[n_seqs];
+    if (total > 0 && !residues) return fail(SW_EINVAL, "residues is NULL");
+    // Code check, split over threads for big databases.
+    const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(16, total >> 24));
+    std::vector<int64_t> bad(nth, -1);
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            const int64_t lo = total * t / nth, hi = total * (t + 1) / nth;
+            for (int64_t i = lo; i < hi; ++i)
+                if (residues[i] >= alphabet) {
+                    bad[t] = i;
+                    return;
+                }
+        });
+    for (auto &x : th) x.join();
+    for (int t = 0; t < nth; ++t)
+        if (bad[t] >= 0)
+            return fail(SW_EINVAL, "residue code %d at %lld >= alphabet %d", residues[bad[t]],
+                        (long long)bad[t], alphabet);
+    return SW_OK;
+}
+
+// A handle with its streams and events on `device`, and no database yet.
+int db_create(int device, int32_t alphabet, std::unique_ptr<sw_db> &out) {
+    std::unique_ptr<sw_db> db(new sw_db());
+    db->device = device;
+    db->alphabet = alphabet;
+    db->R = alphabet + 1;
+    // Check the multiply-shift division used for pair codes.
+    {
+        const int R = db->R, magic = (65536 + R - 1) / R;
+        for (int a = 0; a < R * R; ++a)
+            if (((a * magic) >> 16) != a / R) return fail(SW_EINVAL, "internal: division check failed");
+    }
+    HIPX(hipSetDevice(db->device));
+    {
+        hipDeviceProp_t p;
+        HIPX(hipGetDeviceProperties(&p, db->device));
+        db->cus = p.multiProcessorCount;
+        db->arch = p.gcnArchName;
+    }
+    HIPX(prepare_kernels());
+    HIPX(hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking));
+    HIPX(hipStreamCreateWithFlags(&db->aux, hipStreamNonBlocking));
+    for (auto &e : db->ev) HIPX(hipEventCreate(&e));
+    HIPX(hipEventCreateWithFlags(&db->fork, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&db->join, hipEventDisableTiming));
+    out = std::move(db);
+    return SW_OK;
+}
+
+// Host side of the device layout: subjects stable-sorted by length; the
+// longest (or, for a database too small to give every SIMD a wavefront,
+// all) form the long list; the rest are dealt into groups of 128 whose pair
+// codes are interleaved [chunk of 4 rows][lane][row] and padded with the
+// zero-score residue (the dummy residue of section III.B.1).
+// long_threshold as in sw_db_opts; cus: compute units of the target device.
+int pack_db(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, int32_t alphabet,
+            int32_t long_threshold, int cus, Packed &pk) {
+    pk = Packed{};
+    pk.n_seqs = n_seqs;
+    pk.alphabet = alphabet;
+    pk.total_res = offsets[n_seqs];
+    const int R = alphabet + 1;
+    pk.len.resize(n_seqs);
+    for (int64_t i = 0; i < n_seqs; ++i) {
+        pk.len[i] = offsets[i + 1] - offsets[i];
+        pk.max_len = std::max(pk.max_len, pk.len[i]);
+    }
+    std::vector<int32_t> order(n_seqs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return pk.len[x] < pk.len[y]; });
+
+    // ---- split: lane-per-subject groups vs the long list ----
+    const int64_t simds = 4LL * cus;
+    int64_t cut;   // subjects longer than cut go to the long list
+    pk.fixed_cut = long_threshold != 0;
+    if (long_threshold == -1) cut = INT64_MAX;
+    else if (long_threshold == 1) cut = -1;
+    else if (long_threshold > 1) cut = long_threshold;
+    else if (n_seqs < simds * kGroup) cut = -1;   // cannot give every SIMD a wavefront
+    else cut = kGroupMaxLen;   // each search routes its own cut below this (route_cut)
+    int64_t n_short = 0;
+    while (n_short < n_seqs && pk.len[order[n_short]] <= cut) ++n_short;
+    pk.long_threshold = cut;
+    for (int64_t i = n_seqs - 1; i >= n_short; --i) {
+        pk.long_ids.push_back(order[i]);
+        pk.long_res += pk.len[order[i]];
+    }
+
+    // ---- groups of 128 (lane l: lo = 128g + l, hi = 128g + 64 + l) ----
+    const int32_t ng = (int32_t)((n_short + kGroup - 1) / kGroup);
+    pk.n_groups = ng;
+    pk.gbase.resize(ng);
+    pk.grp_ids.assign((size_t)ng * kGroup, -1);
+    pk.grp_rows.resize(ng);
+    int64_t codes_total = 0;
+    for (int32_t g = 0; g < ng; ++g) {
+        const int64_t last = std::min<int64_t>(n_short, (int64_t)(g + 1) * kGroup) - 1;
+        const int64_t rows = std::max<int64_t>(kChunk, round_up(pk.len[order[last]], kChunk));
+        pk.grp_rows[g] = (int32_t)rows;
+        pk.gbase[g] = codes_total;
+        codes_total += rows * kWave;
+        pk.max_rows = std::max<int32_t>(pk.max_rows, (int32_t)rows);
+        pk.inter_padded_rows += rows * kGroup;
+        pk.grp_res_prefix.push_back(pk.inter_res);
+        for (int x = 0; x < kGroup; ++x) {
+            const int64_t si = (int64_t)g * kGroup + x;
+            if (si < n_short) {
+                pk.grp_ids[(size_t)g * kGroup + x] = order[si];
+                pk.inter_res += pk.len[order[si]];
+            }
+        }
+    }
+    pk.grp_res_prefix.push_back(pk.inter_res);
+    pk.codes.resize((size_t)codes_total);
+    const int nth = (int)std::max(1, std::min(16, ng / 64));
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t)
+        th.emplace_back([&, t] {
+            const uint16_t padc = (uint16_t)(R - 1);
+            for (int32_t g = t; g < ng; g += nth) {
+                const int64_t rows = pk.grp_rows[g];
+                uint16_t *dst = pk.codes.data() + pk.gbase[g];
+                for (int l = 0; l < kWave; ++l) {
+                    const int32_t lo = pk.grp_ids[(size_t)g * kGroup + l];
+                    const int32_t hi = pk.grp_ids[(size_t)g * kGroup + kWave + l];
+                    const uint8_t *slo = lo >= 0 ? residues + offsets[lo] : nullptr;
+                    const uint8_t *shi = hi >= 0 ? residues + offsets[hi] : nullptr;
+                    const int64_t nlo = lo >= 0 ? pk.len[lo] : 0, nhi = hi >= 0 ? pk.len[hi] : 0;
+                    for (int64_t i = 0; i < rows; ++i) {
+                        const uint16_t a = i < nlo ? slo[i] : padc;
+                        const uint16_t b = i < nhi ? shi[i] : padc;
+                        // chunk i/4, lane l, row i%4
+                        dst[(i / kChunk) * (kWave * kChunk) + l * kChunk + (i % kChunk)] =
+                            (uint16_t)(a * R + b);
+                    }
+                }
+            }
+        });
+    for (auto &x : th) x.join();
+    return SW_OK;
+}
+
+// A packed database in memory: the arrays of a Packed, or of one chunk of an
+// on-disk index (mapped).
+struct PackedView {
+    int64_t n_seqs = 0, total_res = 0, max_len = 0;
+    int64_t long_res = 0, long_threshold = 0, inter_res = 0, inter_padded_rows = 0;
+    int32_t n_groups = 0, max_rows = 0, n_long = 0;
+    bool fixed_cut = false;
+    int64_t n_codes = 0;
+    const uint8_t *residues = nullptr;
+    const int64_t *offsets = nullptr;        // n_seqs + 1
+    const int32_t *long_ids = nullptr;       // n_long
+    const int32_t *grp_rows = nullptr;       // n_groups
+    const int32_t *grp_ids = nullptr;        // n_groups * 128
+    const int64_t *grp_res_prefix = nullptr; // n_groups + 1
+    const int64_t *gbase = nullptr;          // n_groups
+    const uint16_t *codes = nullptr;         // n_codes
+};
+
+PackedView view_of(const Packed &pk, const uint8_t *residues, const int64_t *offsets) {
+    PackedView v;
+    v.n_seqs = pk.n_seqs;
+    v.total_res = pk.total_res;
+    v.max_len = pk.max_len;
+    v.long_res = pk.long_res;
+    v.long_threshold = pk.long_threshold;
+    v.inter_res = pk.inter_res;
+    v.inter_padded_rows = pk.inter_padded_rows;
+    v.n_groups = pk.n_groups;
+    v.max_rows = pk.max_rows;
+    v.n_long = (int32_t)pk.long_ids.size();
+    v.fixed_cut = pk.fixed_cut;
+    v.n_codes = (int64_t)pk.codes.size();
+    v.residues = residues;
+    v.offsets = offsets;
+    v.long_ids = pk.long_ids.data();
+    v.grp_rows = pk.grp_rows.data();
+    v.grp_ids = pk.grp_ids.data();
+    v.grp_res_prefix = pk.grp_res_prefix.data();
+    v.gbase = pk.gbase.data();
+    v.codes = pk.codes.data();
+    return v;
+}
+
+// Device bytes of a packed database (residues, offsets, codes, group tables,
+// long list).
+int64_t view_device_bytes(const PackedView &v) {
+    return v.total_res + (v.n_seqs + 1) * 8 + v.n_codes * 2 +
+           (int64_t)v.n_groups * (8 + 4 + kGroup * 4) + (int64_t)v.n_long * 4;
+}
+
+// Make `db` the packed database `v`: host fields copied from it, device
+// copies on `st`, waited for before returning (v's memory may go away then).
+// Device buffers only grow, so a handle reloaded with chunk after chunk keeps
+// the largest chunk's allocation.
+int db_install(sw_db *db, const PackedView &v, hipStream_t st) {
+    HIPX(hipSetDevice(db->device));
+    if (db->graph) {
+        (void)hipGraphExecDestroy(db->graph);
+        db->graph = nullptr;
+        db->graph_key.clear();
+    }
+    const int64_t n = v.n_seqs, total = v.total_res;
+    const int32_t ng = v.n_groups;
+    db->n_seqs = n;
+    db->total_res = total;
+    db->max_len = v.max_len;
+    db->len.resize(n);
+    for (int64_t i = 0; i < n; ++i) db->len[i] = v.offsets[i + 1] - v.offsets[i];
+    db->n_groups = ng;
+    db->max_rows = v.max_rows;
+    db->grp_rows.assign(v.grp_rows, v.grp_rows + ng);
+    db->inter_res = v.inter_res;
+    db->inter_padded_rows = v.inter_padded_rows;
+    db->grp_res_prefix.assign(v.grp_res_prefix, v.grp_res_prefix + ng + 1);
+    db->long_ids.assign(v.long_ids, v.long_ids + v.n_long);
+    db->long_res = v.long_res;
+    db->long_threshold = v.long_threshold;
+    db->fixed_cut = v.fixed_cut;
+    db->grp_ids.assign(v.grp_ids, v.grp_ids + (size_t)ng * kGroup);
+    db->tuned.clear();
+    {
+        char sig[512];
+        snprintf(sig, sizeof sig, "%s|cu%d|n%lld|res%lld|A%d|max%lld", db->arch.c_str(), db->cus,
+                 (long long)n, (long long)total, db->alphabet, (long long)db->max_len);
+        db->signature = sig;
+    }
+    TRY(db->d_res.reserve((size_t)std::max<int64_t>(total, 1)));
+    TRY(db->d_off.reserve((size_t)(n + 1) * 8));
+    if (total > 0) HIPX(hipMemcpyAsync(db->d_res.p, v.residues, (size_t)total, hipMemcpyHostToDevice, st));
+    HIPX(hipMemcpyAsync(db->d_off.p, v.offsets, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st));
+    if (ng > 0) {
+        TRY(db->d_codes.reserve((size_t)v.n_codes * 2));
+        TRY(db->d_grp_base.reserve((size_t)ng * 8));
+        TRY(db->d_grp_rows.reserve((size_t)ng * 4));
+        TRY(db->d_grp_ids.reserve((size_t)ng * kGroup * 4));
+        HIPX(hipMemcpyAsync(db->d_codes.p, v.codes, (size_t)v.n_codes * 2, hipMemcpyHostToDevice, st));
+        HIPX(hipMemcpyAsync(db->d_grp_base.p, v.gbase, (size_t)ng * 8, hipMemcpyHostToDevice, st));
+        HIPX(hipMemcpyAsync(db->d_grp_rows.p, v.grp_rows, (size_t)ng * 4, hipMemcpyHostToDevice, st));
+        HIPX(hipMemcpyAsync(db->d_grp_ids.p, v.grp_ids, (size_t)ng * kGroup * 4,
+                            hipMemcpyHostToDevice, st));
+    }
+    HIPX(hipStreamSynchronize(st));
+    return SW_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 extern "C" {
@@ -1457,169 +1802,13 @@ int sw_db_open(const uint8_t *residues, const int64_t *offsets, int64_t n_seqs, 
     g_err.clear();
     if (!out) return fail(SW_EINVAL, "out is NULL");
     *out = nullptr;
-    if (n_seqs < 0) return fail(SW_EINVAL, "n_seqs < 0");
-    if (alphabet < 1 || alphabet > SW_MAX_ALPHABET)
-        return fail(SW_EINVAL, "alphabet %d not in 1..%d", alphabet, SW_MAX_ALPHABET);
-    if (!offsets) return fail(SW_EINVAL, "offsets is NULL");
-    if (offsets[0] != 0) return fail(SW_EINVAL, "offsets[0] != 0");
-    int64_t max_len = 0;
-    for (int64_t i = 0; i < n_seqs; ++i) {
-        const int64_t L = offsets[i + 1] - offsets[i];
-        if (L < 0) return fail(SW_EINVAL, "offsets decrease at %lld", (long long)i);
-        if (L > SW_MAX_LEN) return fail(SW_EINVAL, "sequence %lld longer than 2^24", (long long)i);
-        max_len = std::max(max_len, L);
-    }
-    const int64_t total = offsets[n_seqs];
-    if (total > 0 && !residues) return fail(SW_EINVAL, "residues is NULL");
-    {
-        // Code check, split over threads for big databases.
-        const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(16, total >> 24));
-        std::vector<int64_t> bad(nth, -1);
-        std::vector<std::thread> th;
-        for (int t = 0; t < nth; ++t)
-            th.emplace_back([&, t] {
-                const int64_t lo = total * t / nth, hi = total * (t + 1) / nth;
-                for (int64_t i = lo; i < hi; ++i)
-                    if (residues[i] >= alphabet) {
-                        bad[t] = i;
-                        return;
-                    }
-            });
-        for (auto &x : th) x.join();
-        for (int t = 0; t < nth; ++t)
-            if (bad[t] >= 0)
-                return fail(SW_EINVAL, "residue code %d at %lld >= alphabet %d", residues[bad[t]],
-                            (long long)bad[t], alphabet);
-    }
-    if (n_seqs > INT32_MAX - 1) return fail(SW_EINVAL, "too many sequences");
-
-    std::unique_ptr<sw_db> db(new sw_db());
-    db->device = opts && opts->device > 0 ? opts->device : 0;
-    db->n_seqs = n_seqs;
-    db->alphabet = alphabet;
-    db->R = alphabet + 1;
-    db->total_res = total;
-    db->max_len = max_len;
-    const int R = db->R;
-    // Check the multiply-shift division used for pair codes.
-    {
-        const int magic = (65536 + R - 1) / R;
-        for (int a = 0; a < R * R; ++a)
-            if (((a * magic) >> 16) != a / R) return fail(SW_EINVAL, "internal: division check failed");
-    }
-    HIPX(hipSetDevice(db->device));
-    {
-        hipDeviceProp_t p;
-        HIPX(hipGetDeviceProperties(&p, db->device));
-        db->cus = p.multiProcessorCount;
-        char sig[512];
-        snprintf(sig, sizeof sig, "%s|cu%d|n%lld|res%lld|A%d|max%lld", p.gcnArchName,
-                 p.multiProcessorCount, (long long)n_seqs, (long long)total, alphabet,
-                 (long long)max_len);
-        db->signature = sig;
-    }
-    HIPX(prepare_kernels());
-    HIPX(hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking));
-    HIPX(hipStreamCreateWithFlags(&db->aux, hipStreamNonBlocking));
-    for (auto &e : db->ev) HIPX(hipEventCreate(&e));
-    HIPX(hipEventCreateWithFlags(&db->fork, hipEventDisableTiming));
-    HIPX(hipEventCreateWithFlags(&db->join, hipEventDisableTiming));
-
-    db->len.resize(n_seqs);
-    for (int64_t i = 0; i < n_seqs; ++i) db->len[i] = offsets[i + 1] - offsets[i];
-    std::vector<int32_t> order(n_seqs);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int32_t x, int32_t y) { return db->len[x] < db->len[y]; });
-
-    // ---- split: lane-per-subject groups vs the long list ----
-    const int64_t simds = 4LL * db->cus;
-    int64_t cut;   // subjects longer than cut go to the long list
-    const int32_t lt = opts ? opts->long_threshold : 0;
-    db->fixed_cut = lt != 0;
-    if (lt == -1) cut = INT64_MAX;
-    else if (lt == 1) cut = -1;
-    else if (lt > 1) cut = lt;
-    else if (n_seqs < simds * kGroup) cut = -1;   // cannot give every SIMD a wavefront
-    else cut = kGroupMaxLen;   // each search routes its own cut below this (route_cut)
-    int64_t n_short = 0;
-    while (n_short < n_seqs && db->len[order[n_short]] <= cut) ++n_short;
-    db->long_threshold = cut;
-    for (int64_t i = n_seqs - 1; i >= n_short; --i) {
-        db->long_ids.push_back(order[i]);
-        db->long_res += db->len[order[i]];
-    }
-
-    // ---- groups of 128 (lane l: lo = 128g + l, hi = 128g + 64 + l) ----
-    const int32_t ng = (int32_t)((n_short + kGroup - 1) / kGroup);
-    db->n_groups = ng;
-    std::vector<int64_t> gbase(ng);
-    std::vector<int32_t> gids((size_t)ng * kGroup, -1);
-    db->grp_rows.resize(ng);
-    int64_t codes_total = 0;
-    for (int32_t g = 0; g < ng; ++g) {
-        const int64_t last = std::min<int64_t>(n_short, (int64_t)(g + 1) * kGroup) - 1;
-        const int64_t rows = std::max<int64_t>(kChunk, round_up(db->len[order[last]], kChunk));
-        db->grp_rows[g] = (int32_t)rows;
-        gbase[g] = codes_total;
-        codes_total += rows * kWave;
-        db->max_rows = std::max<int32_t>(db->max_rows, (int32_t)rows);
-        db->inter_padded_rows += rows * kGroup;
-        db->grp_res_prefix.push_back(db->inter_res);
-        for (int x = 0; x < kGroup; ++x) {
-            const int64_t si = (int64_t)g * kGroup + x;
-            if (si < n_short) {
-                gids[(size_t)g * kGroup + x] = order[si];
-                db->inter_res += db->len[order[si]];
-            }
-        }
-    }
-    db->grp_res_prefix.push_back(db->inter_res);
-    std::vector<uint16_t> codes((size_t)codes_total);
-    {
-        const int nth = (int)std::max(1, std::min(16, ng / 64));
-        std::vector<std::thread> th;
-        for (int t = 0; t < nth; ++t)
-            th.emplace_back([&, t] {
-                const uint16_t padc = (uint16_t)(R - 1);
-                for (int32_t g = t; g < ng; g += nth) {
-                    const int64_t rows = db->grp_rows[g];
-                    uint16_t *dst = codes.data() + gbase[g];
-                    for (int l = 0; l < kWave; ++l) {
-                        const int32_t lo = gids[(size_t)g * kGroup + l];
-                        const int32_t hi = gids[(size_t)g * kGroup + kWave + l];
-                        const uint8_t *slo = lo >= 0 ? residues + offsets[lo] : nullptr;
-                        const uint8_t *shi = hi >= 0 ? residues + offsets[hi] : nullptr;
-                        const int64_t nlo = lo >= 0 ? db->len[lo] : 0, nhi = hi >= 0 ? db->len[hi] : 0;
-                        for (int64_t i = 0; i < rows; ++i) {
-                            const uint16_t a = i < nlo ? slo[i] : padc;
-                            const uint16_t b = i < nhi ? shi[i] : padc;
-                            // chunk i/4, lane l, row i%4
-                            dst[(i / kChunk) * (kWave * kChunk) + l * kChunk + (i % kChunk)] =
-                                (uint16_t)(a * R + b);
-                        }
-                    }
-                }
-            });
-        for (auto &x : th) x.join();
-    }
-
-    // ---- upload ----
-    TRY(db->d_res.reserve((size_t)std::max<int64_t>(total, 1)));
-    TRY(db->d_off.reserve((size_t)(n_seqs + 1) * 8));
-    if (total > 0) HIPX(hipMemcpy(db->d_res.p, residues, (size_t)total, hipMemcpyHostToDevice));
-    HIPX(hipMemcpy(db->d_off.p, offsets, (size_t)(n_seqs + 1) * 8, hipMemcpyHostToDevice));
-    if (ng > 0) {
-        TRY(db->d_codes.reserve(codes.size() * 2));
-        TRY(db->d_grp_base.reserve((size_t)ng * 8));
-        TRY(db->d_grp_rows.reserve((size_t)ng * 4));
-        TRY(db->d_grp_ids.reserve(gids.size() * 4));
-        HIPX(hipMemcpy(db->d_codes.p, codes.data(), codes.size() * 2, hipMemcpyHostToDevice));
-        HIPX(hipMemcpy(db->d_grp_base.p, gbase.data(), (size_t)ng * 8, hipMemcpyHostToDevice));
-        HIPX(hipMemcpy(db->d_grp_rows.p, db->grp_rows.data(), (size_t)ng * 4, hipMemcpyHostToDevice));
-        HIPX(hipMemcpy(db->d_grp_ids.p, gids.data(), gids.size() * 4, hipMemcpyHostToDevice));
-    }
-    db->grp_ids = std::move(gids);
+    TRY(validate_db(residues, offsets, n_seqs, alphabet));
+    const int device = opts && opts->device > 0 ? opts->device : 0;
+    std::unique_ptr<sw_db> db;
+    TRY(db_create(device, alphabet, db));
+    Packed pk;
+    TRY(pack_db(residues, offsets, n_seqs, alphabet, opts ? opts->long_threshold : 0, db->cus, pk));
+    TRY(db_install(db.get(), view_of(pk, residues, offsets), db->stream));
     *out = db.release();
     return SW_OK;
 }
@@ -1660,6 +1849,8 @@ int sw_db_set_opts(sw_db *db, const sw_search_opts *opts) {
         return fail(SW_EINVAL, "6 waves per workgroup runs with strip 32");
     if (opts->sat_threshold < 0) return fail(SW_EINVAL, "sat_threshold < 0");
     if (opts->graph < -1 || opts->graph > 0) return fail(SW_EINVAL, "graph must be 0 or -1");
+    if (opts->profile != SW_PROFILE_PAIR && opts->profile != SW_PROFILE_SCORE)
+        return fail(SW_EINVAL, "profile must be SW_PROFILE_PAIR or SW_PROFILE_SCORE");
     db->opts = *opts;
     return SW_OK;
 }
@@ -1969,6 +2160,426 @@ void sw_server_stop(sw_server *srv) {
         srv->db->server_attached = false;
     }
     delete srv;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Databases larger than device memory (section III's workflow: the database is
+// sorted and indexed offline, and loaded chunk by chunk).
+//
+// sw_index_write sorts the subjects by length, cuts that order into chunks of
+// about chunk_residues residues, and writes each chunk already packed (the
+// device layout of sw_db_open) with its subjects in ascending database order,
+// so a chunk's local index order is the global order.  sw_index_open maps the
+// file; a search keeps the whole index on the device when it fits the memory
+// budget, and otherwise streams it through two chunk slots, loading chunk c+1
+// on a host thread while chunk c is searched.  Per-chunk top-k lists merge by
+// (score desc, global index asc), which gives exactly the top-k of the whole
+// database because ties inside a chunk already break by ascending index.
+// ===========================================================================
+namespace {
+
+constexpr char kIndexMagic[8] = {'S', 'W', 'M', 'I', 'I', 'D', 'X', '1'};
+constexpr int kIndexVersion = 1;
+// Compute units assumed when the writer packs a chunk (MI355X): it decides
+// whether a chunk is large enough to use the lane-per-subject kernel.
+constexpr int kIndexCUs = 256;
+
+struct IndexHeader {
+    char magic[8];
+    int32_t version, alphabet;
+    int64_t n_seqs, total_res, n_chunks, chunk_residues;
+    int64_t reserved[4];
+};
+
+struct ChunkEntry {
+    int64_t file_off;      // first byte of the chunk's section
+    int64_t bytes;         // bytes of the section
+    int64_t n_seqs, total_res, device_bytes;
+};
+
+// Fixed part of a chunk section; the arrays follow, each starting at a
+// multiple of 64 bytes: ids (int32 n), offsets (int64 n+1), residues (uint8),
+// long_ids (int32), grp_rows (int32 ng), grp_ids (int32 ng*128),
+// grp_res_prefix (int64 ng+1), gbase (int64 ng), codes (uint16).
+struct ChunkHead {
+    int64_t n_seqs, total_res, max_len, long_res, long_threshold, inter_res, inter_padded_rows;
+    int64_t n_codes;
+    int32_t n_groups, max_rows, n_long, fixed_cut;
+};
+
+int64_t al64(int64_t x) { return (x + 63) / 64 * 64; }
+
+struct ChunkLayout {
+    int64_t ids, offsets, residues, long_ids, grp_rows, grp_ids, grp_res_prefix, gbase, codes, end;
+};
+
+ChunkLayout chunk_layout(const ChunkHead &h) {
+    ChunkLayout L;
+    int64_t o = al64(sizeof(ChunkHead));
+    L.ids = o;             o = al64(o + h.n_seqs * 4);
+    L.offsets = o;         o = al64(o + (h.n_seqs + 1) * 8);
+    L.residues = o;        o = al64(o + h.total_res);
+    L.long_ids = o;        o = al64(o + (int64_t)h.n_long * 4);
+    L.grp_rows = o;        o = al64(o + (int64_t)h.n_groups * 4);
+    L.grp_ids = o;         o = al64(o + (int64_t)h.n_groups * kGroup * 4);
+    L.grp_res_prefix = o;  o = al64(o + ((int64_t)h.n_groups + 1) * 8);
+    L.gbase = o;           o = al64(o + (int64_t)h.n_groups * 8);
+    L.codes = o;           o = al64(o + h.n_codes * 2);
+    L.end = o;
+    return L;
+}
+
+int write_all(FILE *f, const void *p, size_t n, int64_t at) {
+    if (fseeko(f, (off_t)at, SEEK_SET) != 0) return fail(SW_EINVAL, "index: seek failed");
+    if (n && fwrite(p, 1, n, f) != n) return fail(SW_ENOMEM, "index: write failed (disk full?)");
+    return SW_OK;
+}
+
+}  // namespace
+
+struct sw_index {
+    int device = 0;
+    int fd = -1;
+    const uint8_t *map = nullptr;
+    size_t map_bytes = 0;
+    IndexHeader hdr{};
+    std::vector<ChunkEntry> chunks;
+    bool resident = false;
+    int64_t budget = 0;
+    // resident: one handle per chunk; streaming: two slots
+    std::vector<std::unique_ptr<sw_db>> dbs;
+    std::vector<int> slot_chunk;   // chunk held by each handle (-1 = none)
+    std::mutex mu;
+    sw_index_stats last{};
+};
+
+namespace {
+
+PackedView chunk_view(const sw_index *ix, int64_t c, const int32_t **ids) {
+    const uint8_t *base = ix->map + ix->chunks[c].file_off;
+    ChunkHead h;
+    std::memcpy(&h, base, sizeof h);
+    const ChunkLayout L = chunk_layout(h);
+    PackedView v;
+    v.n_seqs = h.n_seqs;
+    v.total_res = h.total_res;
+    v.max_len = h.max_len;
+    v.long_res = h.long_res;
+    v.long_threshold = h.long_threshold;
+    v.inter_res = h.inter_res;
+    v.inter_padded_rows = h.inter_padded_rows;
+    v.n_groups = h.n_groups;
+    v.max_rows = h.max_rows;
+    v.n_long = h.n_long;
+    v.fixed_cut = h.fixed_cut != 0;
+    v.n_codes = h.n_codes;
+    v.residues = base + L.residues;
+    v.offsets = (const int64_t *)(base + L.offsets);
+    v.long_ids = (const int32_t *)(base + L.long_ids);
+    v.grp_rows = (const int32_t *)(base + L.grp_rows);
+    v.grp_ids = (const int32_t *)(base + L.grp_ids);
+    v.grp_res_prefix = (const int64_t *)(base + L.grp_res_prefix);
+    v.gbase = (const int64_t *)(base + L.gbase);
+    v.codes = (const uint16_t *)(base + L.codes);
+    if (ids) *ids = (const int32_t *)(base + L.ids);
+    return v;
+}
+
+// Load chunk c into handle slot `h` (no-op if it is there already).
+int load_chunk(sw_index *ix, int h, int64_t c, double *ms, int64_t *bytes) {
+    if (ix->slot_chunk[h] == c) return SW_OK;
+    const double t0 = now_ms();
+    ix->slot_chunk[h] = -1;
+    sw_db *db = ix->dbs[h].get();
+    const PackedView v = chunk_view(ix, c, nullptr);
+    TRY(db_install(db, v, db->aux));
+    ix->slot_chunk[h] = (int)c;
+    if (ms) *ms += now_ms() - t0;
+    if (bytes) *bytes += view_device_bytes(v);
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_index_write(const char *path, const uint8_t *residues, const int64_t *offsets,
+                   int64_t n_seqs, int32_t alphabet, int64_t chunk_residues) {
+    g_err.clear();
+    if (!path) return fail(SW_EINVAL, "path is NULL");
+    if (chunk_residues < 1) return fail(SW_EINVAL, "chunk_residues < 1");
+    TRY(validate_db(residues, offsets, n_seqs, alphabet));
+    std::vector<int64_t> len(n_seqs);
+    for (int64_t i = 0; i < n_seqs; ++i) len[i] = offsets[i + 1] - offsets[i];
+    std::vector<int32_t> order(n_seqs);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len[x] < len[y]; });
+    // chunk boundaries in length order (at least one subject per chunk)
+    std::vector<int64_t> cut{0};
+    int64_t acc = 0;
+    for (int64_t i = 0; i < n_seqs; ++i) {
+        if (acc > 0 && acc + len[order[i]] > chunk_residues) {
+            cut.push_back(i);
+            acc = 0;
+        }
+        acc += len[order[i]];
+    }
+    if (n_seqs > 0) cut.push_back(n_seqs);
+    const int64_t n_chunks = (int64_t)cut.size() - 1;
+
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(SW_EINVAL, "index: cannot create %s", path);
+    std::unique_ptr<FILE, int (*)(FILE *)> guard(f, fclose);
+    IndexHeader hdr{};
+    std::memcpy(hdr.magic, kIndexMagic, 8);
+    hdr.version = kIndexVersion;
+    hdr.alphabet = alphabet;
+    hdr.n_seqs = n_seqs;
+    hdr.total_res = offsets[n_seqs];
+    hdr.n_chunks = n_chunks;
+    hdr.chunk_residues = chunk_residues;
+    std::vector<ChunkEntry> table((size_t)n_chunks);
+    int64_t pos = al64((int64_t)sizeof hdr + n_chunks * (int64_t)sizeof(ChunkEntry));
+    for (int64_t c = 0; c < n_chunks; ++c) {
+        // the chunk's subjects in ascending database order
+        std::vector<int32_t> ids(order.begin() + cut[c], order.begin() + cut[c + 1]);
+        std::sort(ids.begin(), ids.end());
+        const int64_t n = (int64_t)ids.size();
+        std::vector<int64_t> loff(n + 1, 0);
+        for (int64_t i = 0; i < n; ++i) loff[i + 1] = loff[i] + len[ids[i]];
+        std::vector<uint8_t> lres((size_t)loff[n]);
+        for (int64_t i = 0; i < n; ++i)
+            std::memcpy(lres.data() + loff[i], residues + offsets[ids[i]], (size_t)len[ids[i]]);
+        Packed pk;
+        TRY(pack_db(lres.data(), loff.data(), n, alphabet, 0, kIndexCUs, pk));
+        ChunkHead h{};
+        h.n_seqs = n;
+        h.total_res = loff[n];
+        h.max_len = pk.max_len;
+        h.long_res = pk.long_res;
+        h.long_threshold = pk.long_threshold;
+        h.inter_res = pk.inter_res;
+        h.inter_padded_rows = pk.inter_padded_rows;
+        h.n_codes = (int64_t)pk.codes.size();
+        h.n_groups = pk.n_groups;
+        h.max_rows = pk.max_rows;
+        h.n_long = (int32_t)pk.long_ids.size();
+        h.fixed_cut = pk.fixed_cut ? 1 : 0;
+        const ChunkLayout L = chunk_layout(h);
+        TRY(write_all(f, &h, sizeof h, pos));
+        TRY(write_all(f, ids.data(), (size_t)n * 4, pos + L.ids));
+        TRY(write_all(f, loff.data(), (size_t)(n + 1) * 8, pos + L.offsets));
+        TRY(write_all(f, lres.data(), lres.size(), pos + L.residues));
+        TRY(write_all(f, pk.long_ids.data(), pk.long_ids.size() * 4, pos + L.long_ids));
+        TRY(write_all(f, pk.grp_rows.data(), pk.grp_rows.size() * 4, pos + L.grp_rows));
+        TRY(write_all(f, pk.grp_ids.data(), pk.grp_ids.size() * 4, pos + L.grp_ids));
+        TRY(write_all(f, pk.grp_res_prefix.data(), pk.grp_res_prefix.size() * 8, pos + L.grp_res_prefix));
+        TRY(write_all(f, pk.gbase.data(), pk.gbase.size() * 8, pos + L.gbase));
+        TRY(write_all(f, pk.codes.data(), pk.codes.size() * 2, pos + L.codes));
+        table[c].file_off = pos;
+        table[c].bytes = L.end;
+        table[c].n_seqs = n;
+        table[c].total_res = loff[n];
+        table[c].device_bytes = view_device_bytes(view_of(pk, lres.data(), loff.data()));
+        pos += L.end;
+    }
+    TRY(write_all(f, &hdr, sizeof hdr, 0));
+    TRY(write_all(f, table.data(), table.size() * sizeof(ChunkEntry), sizeof hdr));
+    // the file ends at the last section's end (zero bytes of padding included)
+    if (ftruncate(fileno(f), (off_t)pos) != 0) return fail(SW_ENOMEM, "index: cannot size %s", path);
+    if (fflush(f) != 0) return fail(SW_ENOMEM, "index: write failed (disk full?)");
+    return SW_OK;
+}
+
+int sw_index_open(const char *path, const sw_index_opts *opts, sw_index **out) {
+    g_err.clear();
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(SW_EINVAL, "path is NULL");
+    std::unique_ptr<sw_index> ix(new sw_index());
+    ix->device = opts && opts->device > 0 ? opts->device : 0;
+    ix->fd = open(path, O_RDONLY);
+    if (ix->fd < 0) return fail(SW_EINVAL, "index: cannot open %s", path);
+    struct stat sb;
+    if (fstat(ix->fd, &sb) != 0 || sb.st_size < (off_t)sizeof(IndexHeader)) {
+        close(ix->fd);
+        return fail(SW_EINVAL, "index: %s is too short", path);
+    }
+    ix->map_bytes = (size_t)sb.st_size;
+    void *m = mmap(nullptr, ix->map_bytes, PROT_READ, MAP_SHARED, ix->fd, 0);
+    if (m == MAP_FAILED) {
+        close(ix->fd);
+        return fail(SW_ENOMEM, "index: cannot map %s", path);
+    }
+    ix->map = (const uint8_t *)m;
+    auto bad = [&](const char *what) {
+        munmap((void *)ix->map, ix->map_bytes);
+        close(ix->fd);
+        return fail(SW_EINVAL, "index: %s: %s", path, what);
+    };
+    std::memcpy(&ix->hdr, ix->map, sizeof ix->hdr);
+    const IndexHeader &h = ix->hdr;
+    if (std::memcmp(h.magic, kIndexMagic, 8) != 0) return bad("not an index file");
+    if (h.version != kIndexVersion) return bad("unknown version");
+    if (h.alphabet < 1 || h.alphabet > SW_MAX_ALPHABET || h.n_seqs < 0 || h.n_chunks < 0 ||
+        (int64_t)sizeof h + h.n_chunks * (int64_t)sizeof(ChunkEntry) > (int64_t)ix->map_bytes)
+        return bad("corrupt header");
+    ix->chunks.resize((size_t)h.n_chunks);
+    std::memcpy(ix->chunks.data(), ix->map + sizeof h, ix->chunks.size() * sizeof(ChunkEntry));
+    int64_t total_dev = 0, max_dev = 0, n_sum = 0;
+    for (const ChunkEntry &c : ix->chunks) {
+        if (c.file_off < 0 || c.bytes < (int64_t)sizeof(ChunkHead) ||
+            c.file_off + c.bytes > (int64_t)ix->map_bytes)
+            return bad("chunk outside the file");
+        ChunkHead ch;
+        std::memcpy(&ch, ix->map + c.file_off, sizeof ch);
+        if (ch.n_seqs != c.n_seqs || chunk_layout(ch).end != c.bytes) return bad("corrupt chunk");
+        total_dev += c.device_bytes;
+        max_dev = std::max(max_dev, c.device_bytes);
+        n_sum += c.n_seqs;
+    }
+    if (n_sum != h.n_seqs) return bad("chunks do not cover the database");
+    madvise((void *)ix->map, ix->map_bytes, MADV_SEQUENTIAL);
+    int64_t budget = opts ? opts->memory_budget : 0;
+    if (budget <= 0) {
+        size_t fr = 0, tot = 0;
+        HIPX(hipSetDevice(ix->device));
+        HIPX(hipMemGetInfo(&fr, &tot));
+        budget = (int64_t)(fr / 2);
+    }
+    ix->budget = budget;
+    ix->resident = total_dev <= budget || h.n_chunks <= 1;
+    if (!ix->resident && 2 * max_dev > budget) {
+        munmap((void *)ix->map, ix->map_bytes);
+        close(ix->fd);
+        return fail(SW_ENOMEM, "index: a memory budget of %lld bytes cannot hold two chunks of up to "
+                    "%lld bytes; write the index with smaller chunks", (long long)budget,
+                    (long long)max_dev);
+    }
+    const int64_t handles = ix->resident ? h.n_chunks : 2;
+    for (int64_t x = 0; x < handles; ++x) {
+        std::unique_ptr<sw_db> db;
+        TRY(db_create(ix->device, h.alphabet, db));
+        ix->dbs.push_back(std::move(db));
+        ix->slot_chunk.push_back(-1);
+    }
+    if (ix->resident)
+        for (int64_t c = 0; c < h.n_chunks; ++c) TRY(load_chunk(ix.get(), (int)c, c, nullptr, nullptr));
+    *out = ix.release();
+    return SW_OK;
+}
+
+void sw_index_close(sw_index *ix) {
+    if (!ix) return;
+    for (auto &db : ix->dbs) sw_db_close(db.release());
+    if (ix->map) munmap((void *)ix->map, ix->map_bytes);
+    if (ix->fd >= 0) close(ix->fd);
+    delete ix;
+}
+
+int64_t sw_index_size(const sw_index *ix) { return ix ? ix->hdr.n_seqs : -1; }
+
+int sw_index_last_stats(sw_index *ix, sw_index_stats *out) {
+    g_err.clear();
+    if (!ix || !out) return fail(SW_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(ix->mu);
+    *out = ix->last;
+    return SW_OK;
+}
+
+int sw_index_search_batch(sw_index *ix, int32_t nq, const uint8_t *q_res, const int64_t *q_off,
+                          const sw_scoring *sc, int32_t k, int32_t *top_scores, int64_t *top_idx,
+                          int32_t *all_scores) {
+    g_err.clear();
+    if (!ix) return fail(SW_EINVAL, "index is NULL");
+    if (k < 1 || k > SW_MAX_K) return fail(SW_EINVAL, "k not in 1..%d", SW_MAX_K);
+    if (!top_scores || !top_idx) return fail(SW_EINVAL, "top-k outputs are NULL");
+    if (nq < 1) return fail(SW_EINVAL, "nq < 1");
+    if (!q_res || !q_off) return fail(SW_EINVAL, "queries are NULL");
+    std::lock_guard<std::mutex> lk(ix->mu);
+    const double t_start = now_ms();
+    const int64_t N = ix->hdr.n_seqs;
+    if ((int64_t)nq * N > ((int64_t)1 << 40)) return fail(SW_EINVAL, "batch too large");
+    // running top-k per query: (score, global index), -1 fill
+    std::vector<int32_t> best_s((size_t)nq * k, -1);
+    std::vector<int64_t> best_i((size_t)nq * k, -1);
+    sw_index_stats st{};
+    st.chunks = (int64_t)ix->chunks.size();
+    st.resident = ix->resident ? 1 : 0;
+    if (ix->chunks.empty()) {
+        if (nq > 0) {
+            std::copy(best_s.begin(), best_s.end(), top_scores);
+            std::copy(best_i.begin(), best_i.end(), top_idx);
+        }
+        ix->last = st;
+        return SW_OK;
+    }
+    std::vector<int32_t> cs((size_t)nq * k), chunk_scores;
+    std::vector<int64_t> ci((size_t)nq * k);
+    std::vector<std::pair<int32_t, int64_t>> cand;
+    const int64_t nc = (int64_t)ix->chunks.size();
+    // streaming: chunk c in slot c % 2, chunk 0 loaded before the loop
+    if (!ix->resident) TRY(load_chunk(ix, 0, 0, &st.load_ms, &st.bytes_loaded));
+    for (int64_t c = 0; c < nc; ++c) {
+        const int h = ix->resident ? (int)c : (int)(c % 2);
+        std::thread loader;
+        int load_rc = SW_OK;
+        std::string load_err;
+        double load_ms = 0;
+        int64_t load_bytes = 0;
+        if (!ix->resident && c + 1 < nc) {
+            loader = std::thread([&, c] {
+                load_rc = load_chunk(ix, (int)((c + 1) % 2), c + 1, &load_ms, &load_bytes);
+                if (load_rc != SW_OK) load_err = g_err;
+            });
+        }
+        const int32_t *ids = nullptr;
+        const PackedView v = chunk_view(ix, c, &ids);
+        sw_db *db = ix->dbs[h].get();
+        int rc;
+        {
+            std::lock_guard<std::mutex> dlk(db->mu);
+            if (all_scores) chunk_scores.resize((size_t)nq * std::max<int64_t>(v.n_seqs, 1));
+            const double t0 = now_ms();
+            rc = run_search(db, nq, q_res, q_off, sc, k, cs.data(), ci.data(),
+                            all_scores ? chunk_scores.data() : nullptr, nullptr, nullptr);
+            st.search_ms += now_ms() - t0;
+            st.kernel_ms += db->last.kernel_ms;
+            st.cells += db->last.cells;
+        }
+        if (loader.joinable()) loader.join();
+        if (rc != SW_OK) return rc;
+        if (load_rc != SW_OK) return fail(load_rc, "%s", load_err.c_str());
+        st.load_ms += load_ms;
+        st.bytes_loaded += load_bytes;
+        // merge: local index -> global, then (score desc, global index asc)
+        for (int32_t q = 0; q < nq; ++q) {
+            cand.clear();
+            for (int32_t x = 0; x < k; ++x) {
+                const size_t a = (size_t)q * k + x;
+                if (best_i[a] >= 0) cand.push_back({best_s[a], best_i[a]});
+                if (ci[a] >= 0) cand.push_back({cs[a], (int64_t)ids[ci[a]]});
+            }
+            std::sort(cand.begin(), cand.end(), [](const auto &a, const auto &b) {
+                return a.first != b.first ? a.first > b.first : a.second < b.second;
+            });
+            for (int32_t x = 0; x < k; ++x) {
+                const size_t a = (size_t)q * k + x;
+                best_s[a] = x < (int32_t)cand.size() ? cand[x].first : -1;
+                best_i[a] = x < (int32_t)cand.size() ? cand[x].second : -1;
+            }
+            if (all_scores)
+                for (int64_t i = 0; i < v.n_seqs; ++i)
+                    all_scores[(size_t)q * N + ids[i]] = chunk_scores[(size_t)q * v.n_seqs + i];
+        }
+    }
+    std::copy(best_s.begin(), best_s.end(), top_scores);
+    std::copy(best_i.begin(), best_i.end(), top_idx);
+    st.total_ms = now_ms() - t_start;
+    ix->last = st;
+    return SW_OK;
 }
 
 }  // extern "C"

@@ -47,6 +47,9 @@ enum Tier : int { TIER_F16X2 = 1, TIER_I16X2 = 2 };
 // of the score matrix.
 struct QuerySet {
     const int8_t *const *qp;
+    // score-profile kernel only: per slot, the A x A matrix followed by the
+    // mpad query codes (past the query: the pad letter A); nullptr otherwise
+    const uint8_t *const *qc;
     const int32_t *mpad;     // padded length (multiple of kQPad, even)
     const int32_t *qlen;     // real length
     const int32_t *gap;      // alpha, beta of slot q at gap[2q], gap[2q+1]
@@ -108,6 +111,13 @@ hipError_t launch_inter(const InterArgs &a, const IntraArgs *la, int ti, int tie
 int inter_lds_bytes(int R, int strip, int ti = 0, int waves = 4);
 // resident workgroups that fit (ti as for launch_inter)
 int inter_max_grid(int R, int tier, int strip, int waves, int ti = 0);
+
+// Score-profile variant of the lane-per-subject kernel (fp16 tier, strip 32,
+// 4 waves per workgroup, alphabets of at most 23 letters); needs qs.qc.
+hipError_t launch_inter_sp(const InterArgs &a, int strip, int waves, int grid, hipStream_t st);
+int inter_sp_lds_bytes(int R, int waves);
+int inter_sp_max_grid(int R, int waves);
+constexpr int kSpMaxAlphabet = 23;
 
 hipError_t launch_intra(const IntraArgs &a, int T, int waves, int grid, hipStream_t st);
 int intra_lds_bytes(int R, int T);

@@ -59,6 +59,8 @@
 //   I16X2: saturating int16; thr = 32767, the saturation ceiling.
 #include "sw_internal.h"
 
+#include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 namespace swmi {
@@ -684,6 +686,289 @@ hipError_t launch_inter(const InterArgs &a, const IntraArgs *la, int ti, int tie
     if (tier == TIER_F16X2) return launch_inter_tier<TIER_F16X2>(a, la, ti, strip, waves, grid, st);
     if (tier == TIER_I16X2) return launch_inter_tier<TIER_I16X2>(a, la, ti, strip, waves, grid, st);
     return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// Score-profile variant of the lane-per-subject kernel (section III.B.3).
+//
+// The paper's score profile holds, for the subject residues under the vector
+// lanes, their scores against every query letter, so the inner loop over
+// query positions reads it at the query letter instead of gathering.  Here
+// each lane keeps the score-profile row of its own two subjects' residues at
+// one subject row: SP[c][lane] = (M[c][s_lo] + 2 alpha, M[c][s_hi] + 2 alpha)
+// for every query letter c, one dword per letter, lane-contiguous in LDS, so
+// the read for query column j (letter q_j, the same for the whole wave) is
+// conflict-free.  The row is copied, one row ahead, from a letter-pair table
+// LPT[a * R + b][c] built once per query in the workgroup's LDS (it depends
+// only on the matrix and alpha).  Each lane's T column addresses
+// (letter q_j x 256 + lane x 4) are set once per strip.  The pad letter A
+// scores 0 (columns past the query).  The arithmetic is FrameStrip's; a
+// class-0 column takes its diagonal bias (2 - G) alpha as the table's 2 alpha
+// plus -G alpha on the diagonal operand.
+// ---------------------------------------------------------------------------
+constexpr int kSpLetters = 24;   // letters per table row: query alphabet + pad letter, <= 24
+
+template <int T>
+struct FrameStripSP {
+    static_assert(kFrameCols == 4 && T % kFrameCols == 0, "column classes");
+    typedef h2 V;
+    typedef FrameStrip<T> F;
+
+    // Write one profile row (the table row `t` of a subject row's pair code)
+    // into this lane's column of the wave's profile buffer.
+    static __device__ __forceinline__ void put(uint32_t *spw, const uint4 *t) {
+        uint4 L[kSpLetters / 4];
+#pragma unroll
+        for (int c4 = 0; c4 < kSpLetters / 4; ++c4) L[c4] = t[c4];
+#pragma unroll
+        for (int c4 = 0; c4 < kSpLetters / 4; ++c4) {
+            spw[(4 * c4 + 0) * kWave] = L[c4].x;
+            spw[(4 * c4 + 1) * kWave] = L[c4].y;
+            spw[(4 * c4 + 2) * kWave] = L[c4].z;
+            spw[(4 * c4 + 3) * kWave] = L[c4].w;
+        }
+    }
+
+    // One subject row: P holds its T values.  First the next row's profile
+    // row is put in the buffer (table row `tn`); the row is computed; then P
+    // is refilled with the next row's values.  The LDS latencies of the copy
+    // and the refill are covered by the SIMD's other wave.
+    static __device__ __forceinline__ void row(const LaneFrame &ops, V (&H)[T], V (&E)[T],
+                                               uint32_t (&P)[T], const uint4 *tn, uint32_t *spw,
+                                               const uint32_t (&addr)[T], const uint8_t *lds8,
+                                               uint32_t hb_prev, uint32_t fin, const V *FL,
+                                               V (&B)[2], uint32_t &hout, uint32_t &fout) {
+        put(spw, tn);
+        V hdiag = as_v<V>(hb_prev);
+        V f = as_v<V>(fin);
+#pragma unroll
+        for (int j4 = 0; j4 < T / 4; ++j4) {
+            const int j = j4 * 4;
+            V hd0 = hdiag + ops.ngroup;
+            const V h0 = F::template cell<0>(ops, H[j], E[j], P[j], hd0, f, FL[0]);
+            hdiag = hd0;   // cell<0> leaves H(r-1, j) here
+            F::template cell<1>(ops, H[j + 1], E[j + 1], P[j + 1], hdiag, f, FL[1]);
+            B[0] = F::max3(B[0], h0, hdiag);
+            const V h2v = F::template cell<2>(ops, H[j + 2], E[j + 2], P[j + 2], hdiag, f, FL[2]);
+            F::template cell<3>(ops, H[j + 3], E[j + 3], P[j + 3], hdiag, f, FL[3]);
+            B[1] = F::max3(B[1], h2v, hdiag);
+        }
+        hout = as_u(H[T - 1]);
+        fout = as_u(f);
+#pragma unroll
+        for (int j = 0; j < T; ++j) asm volatile("" : "+v"(H[j]), "+v"(E[j]));
+        asm volatile("" : "+v"(B[0]), "+v"(B[1]));
+#pragma unroll
+        for (int j = 0; j < T; ++j) P[j] = *(const uint32_t *)(lds8 + addr[j]);
+    }
+
+    // All rows of one group against one strip, as FrameStrip::pass.
+    template <bool HAS_IN, bool HAS_OUT>
+    static __device__ __forceinline__ void pass(const LaneFrame &ops, V &best_io,
+                                                const uint16_t *codes, uint32_t *wsc, int nch,
+                                                const uint32_t *lpt, uint32_t *spw,
+                                                const uint32_t (&addr)[T], const uint8_t *lds8) {
+        constexpr int kPeriodChunks = kFrameRows / kChunk;
+        V H[T], E[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) {
+            H[j] = ops.k((j & 3) - 1);
+            E[j] = ops.k(j & 3);
+        }
+        constexpr int kFloors = kChunk + kFrameCols - 1;
+        V FL[kFloors];
+#pragma unroll
+        for (int x = 0; x < kFloors; ++x) FL[x] = ops.k(x + 1);
+        const V chunk_step = ops.k(kChunk);
+        V B[2] = {best_io, ops.k(0)};
+        V z = ops.k(kFrameCols - 2);
+        uint32_t hb_prev = as_u(z);
+        const uint32_t f_edge = as_u(ops.nalpha);
+        const int last = nch - 1;
+        uint2 cd = *(const uint2 *)codes;
+        uint2 cd_n = *(const uint2 *)(codes + (size_t)(last < 1 ? last : 1) * 256);
+        uint4 b0 = make_uint4(0, 0, 0, 0), b1 = make_uint4(0, 0, 0, 0);
+        if (HAS_IN) {
+            b0 = ((const uint4 *)wsc)[0];
+            b1 = ((const uint4 *)wsc)[1];
+        }
+        // prologue: row 0's profile row written and read
+        put(spw, (const uint4 *)(lpt + (cd.x & 0xffffu) * kSpLetters));
+        uint32_t P[T];
+#pragma unroll
+        for (int j = 0; j < T; ++j) P[j] = *(const uint32_t *)(lds8 + addr[j]);
+        for (int c = 0; c < nch; ++c) {
+            if (c != 0 && c % kPeriodChunks == 0) {
+#pragma unroll
+                for (int j = 0; j < T; ++j) { H[j] += ops.rebase; E[j] += ops.rebase; }
+#pragma unroll
+                for (int x = 0; x < kFloors; ++x) FL[x] += ops.rebase;
+                B[0] += ops.rebase;
+                B[1] += ops.rebase;
+                if (HAS_IN) hb_prev = as_u(as_v<V>(hb_prev) + ops.rebase);
+                else z += ops.rebase;
+            }
+            const int c1 = c + 1 < last ? c + 1 : last;
+            const int c2 = c + 2 < last ? c + 2 : last;
+            const uint2 cd_nn = *(const uint2 *)(codes + (size_t)c2 * 256);
+            uint4 b0n = make_uint4(0, 0, 0, 0), b1n = make_uint4(0, 0, 0, 0);
+            if (HAS_IN) {
+                b0n = ((const uint4 *)(wsc + (size_t)c1 * 512))[0];
+                b1n = ((const uint4 *)(wsc + (size_t)c1 * 512))[1];
+            }
+            // table rows of rows x + 1: rows 1, 2, 3 of this chunk and row 0 of the next
+            const uint32_t tn[4] = {cd.x >> 16, cd.y & 0xffffu, cd.y >> 16, cd_n.x & 0xffffu};
+            const uint32_t hb_in[4] = {hb_prev, b0.x, b0.z, b1.x};
+            const uint32_t f_in[4] = {b0.y, b0.w, b1.y, b1.w};
+            uint32_t o[8];
+#pragma unroll
+            for (int x = 0; x < kChunk; ++x) {
+                const uint32_t hb = HAS_IN ? hb_in[x] : as_u(z), fi = HAS_IN ? f_in[x] : f_edge;
+                row(ops, H, E, P, (const uint4 *)(lpt + tn[x] * kSpLetters), spw, addr, lds8, hb, fi,
+                    FL + x, B, o[2 * x], o[2 * x + 1]);
+                B[0] += ops.palpha;
+                B[1] += ops.palpha;
+                if (!HAS_IN) z += ops.palpha;
+            }
+#pragma unroll
+            for (int x = 0; x < kFloors; ++x) FL[x] += chunk_step;
+            hb_prev = b1.z;
+            if (HAS_OUT) {
+                uint4 *dst = (uint4 *)(wsc + (size_t)c * 512);
+                dst[0] = make_uint4(o[0], o[1], o[2], o[3]);
+                dst[1] = make_uint4(o[4], o[5], o[6], o[7]);
+            }
+            cd = cd_n;
+            cd_n = cd_nn;
+            b0 = b0n;
+            b1 = b1n;
+        }
+#pragma unroll
+        for (int j = 0; j < T; j += 4) {
+            B[0] = __builtin_elementwise_maximum(B[0], H[j + 1]);
+            B[1] = __builtin_elementwise_maximum(B[1], H[j + 3]);
+        }
+        best_io = __builtin_elementwise_maximum(B[0] - (FL[0] + ops.nalpha),
+                                                B[1] - (FL[0] + ops.palpha));
+    }
+};
+
+int inter_sp_lds_bytes(int R, int waves) {
+    return (R * R * kSpLetters + waves * kSpLetters * kWave) * 4;
+}
+
+template <int T, int W>
+__global__ void __launch_bounds__(W * 64, 2) inter_sp_kernel(InterArgs a, int magic) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    const int R = a.R;
+    const int RR = R * R;
+    uint32_t *lpt = lds;                                   // RR x kSpLetters
+    uint32_t *spbase = lds + RR * kSpLetters;              // W x kSpLetters x 64
+    __shared__ int s_item;
+    __shared__ int s_q;   // query whose table is in LDS (-1: none)
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    uint32_t *wsc = a.scratch + ((size_t)(blockIdx.x * W + w) * (size_t)a.max_rows) * 128 + lane * 8;
+    uint32_t *spw = spbase + (size_t)w * kSpLetters * kWave + lane;
+    const uint8_t *lds8 = (const uint8_t *)lds;
+    if (threadIdx.x == 0) s_q = -1;
+
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
+        const int last_q = __builtin_amdgcn_readfirstlane(s_q);
+        __syncthreads();   // s_item and s_q read by every wave before either changes
+        if (it >= a.n_items) break;
+        const int q = __builtin_amdgcn_readfirstlane(a.item_q[it]);
+        const int alpha = a.qs.gap[2 * q], beta = a.qs.gap[2 * q + 1];
+        const LaneFrame ops(min(alpha, 2048), min(beta, 2048));
+        const int thr = lane_frame_thr(a.thr, alpha);
+        const int A = R - 1;
+        const uint8_t *blk = a.qs.qc[q];        // A x A matrix, then the mpad query codes
+        const uint8_t *qcodes = blk + A * A;
+        if (q != last_q) {
+            // every wave has finished its previous item (the loop-top barrier)
+            const int8_t *M = (const int8_t *)blk;
+            for (int e = threadIdx.x; e < RR * kSpLetters; e += W * 64) {
+                const int pair = e / kSpLetters, c = e - pair * kSpLetters;
+                const int ra = div_r(pair, magic), rb = pair - ra * R;
+                const int va = c < A && ra < A ? M[c * A + ra] : 0;
+                const int vb = c < A && rb < A ? M[c * A + rb] : 0;
+                lpt[e] = (uint32_t)Lane<TIER_F16X2>::enc(va + ops.bias1) |
+                         ((uint32_t)Lane<TIER_F16X2>::enc(vb + ops.bias1) << 16);
+            }
+            if (threadIdx.x == 0) s_q = q;
+            __syncthreads();
+        }
+        const int g = a.item_g[it] + w;
+        const bool active = g < a.n_groups;
+        if (active) {
+            const int rows = a.grp_rows[g];
+            const int mp = a.qs.mpad[q];
+            const int nstrips = (mp + T - 1) / T;
+            const uint16_t *codes = a.codes + a.grp_base[g] + lane * 4;
+            const int nch = rows / kChunk;
+            const uint32_t spw_off = (uint32_t)((spw - lds) * 4) - (uint32_t)lane * 4;
+            h2 best = Lane<TIER_F16X2>::zero();
+            for (int k = 0; k < nstrips; ++k) {
+                uint32_t addr[T];
+#pragma unroll
+                for (int j = 0; j < T; ++j) {
+                    const int col = k * T + j;
+                    const int letter = col < mp ? qcodes[col] : A;
+                    addr[j] = spw_off + (uint32_t)letter * (kWave * 4) + (uint32_t)lane * 4;
+                }
+                typedef FrameStripSP<T> S;
+                if (k == 0) {
+                    if (nstrips == 1) S::template pass<false, false>(ops, best, codes, wsc, nch, lpt, spw, addr, lds8);
+                    else S::template pass<false, true>(ops, best, codes, wsc, nch, lpt, spw, addr, lds8);
+                } else {
+                    if (k + 1 == nstrips) S::template pass<true, false>(ops, best, codes, wsc, nch, lpt, spw, addr, lds8);
+                    else S::template pass<true, true>(ops, best, codes, wsc, nch, lpt, spw, addr, lds8);
+                }
+            }
+            const int ids[2] = {a.grp_ids[g * kGroup + lane], a.grp_ids[g * kGroup + kWave + lane]};
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                const int id = ids[half];
+                if (id < 0) continue;
+                bool flag;
+                const int v = Lane<TIER_F16X2>::value(best, half, thr, &flag);
+                a.scores[(size_t)q * a.n_seqs + id] = v;
+                if (flag) {
+                    const int pos = atomicAdd(a.ovf_count, 1);
+                    if (pos < a.ovf_cap) {
+                        a.ovf_q[pos] = q;
+                        a.ovf_id[pos] = id;
+                    }
+                }
+            }
+        }
+    }
+}
+
+int inter_sp_max_grid(int R, int waves) {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    int per_cu = 0;
+    if (waves == 4 &&
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, inter_sp_kernel<32, 4>, 4 * 64,
+                                                     inter_sp_lds_bytes(R, 4)) != hipSuccess)
+        per_cu = 0;
+    if (per_cu < 1) per_cu = 1;
+    return per_cu * cus;
+}
+
+hipError_t launch_inter_sp(const InterArgs &a, int strip, int waves, int grid, hipStream_t st) {
+    if (strip != 32 || waves != 4 || a.R - 1 >= kSpLetters) return hipErrorInvalidValue;
+    const int magic = (65536 + a.R - 1) / a.R;
+    hipLaunchKernelGGL((inter_sp_kernel<32, 4>), dim3(grid), dim3(4 * 64), inter_sp_lds_bytes(a.R, 4),
+                       st, a, magic);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -2014,7 +2299,7 @@ hipError_t prepare_kernels() {
         (const void *)intra2_kernel<16, 4>,
         (const void *)align_fwd_kernel<4, kAlignWaves>, (const void *)align_fwd_kernel<8, kAlignWaves>,
         (const void *)align_fwd_kernel<16, kAlignWaves>, (const void *)align_pipe_kernel<4>,
-        (const void *)align_pipe_kernel<8>,
+        (const void *)align_pipe_kernel<8>, (const void *)inter_sp_kernel<32, 4>,
     };
 #undef SWMI_FUSED
 #undef SWMI_K

@@ -73,7 +73,7 @@ def test_null_handle_calls(swmi):
 
 
 STRUCTS = ["sw_scoring", "sw_db_opts", "sw_search_opts", "sw_stats", "sw_server_opts", "sw_req_stats",
-           "sw_alignment"]
+           "sw_alignment", "sw_index_opts", "sw_index_stats"]
 
 
 def test_binding_structs_match_the_header(tmp_path):

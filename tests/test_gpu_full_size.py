@@ -177,6 +177,30 @@ def test_plain_scale_full_size(swmi, orc, plain_db, waves):
     db.set_opts(reset=True)
 
 
+def test_plain_scale_streamed_full_size(swmi, orc, plain_db, tmp_path):
+    """plain_scale through an on-disk index (chunks of 128 M residues) with a
+    1 GiB memory budget: the chunks stream through two device slots, all 20
+    queries in one batch, every score vector against the oracle's digest."""
+    w, res, off, M, rec, db = plain_db
+    qs = w.queries()
+    path = tmp_path / "plain_scale.swx"
+    print("plain_scale streamed: writing the index", flush=True)
+    swmi.sw_index_write(str(path), res, off, 20, 128 << 20)
+    ix = swmi.Index(str(path), memory_budget=1 << 30)
+    try:
+        print("plain_scale streamed: search", flush=True)
+        ts, ti, al = ix.search_batch(qs, M, w.alpha, w.beta, 10, all_scores=True)
+        st = ix.stats()
+    finally:
+        ix.close()
+    os.remove(path)
+    assert st["resident"] == 0 and st["chunks"] >= 5 and st["bytes_loaded"] > (1 << 30)
+    for qi, q in enumerate(qs):
+        e = query_record(rec, "plain_scale", qi, q)
+        check_full(orc, e, q, res, off, M, w, al[qi], ts[qi], ti[qi],
+                   f"plain_scale streamed q{qi}", seed=3030 + qi)
+
+
 def test_batched_full_size(swmi, orc, golden):
     w = sd.WORKLOADS["batched"]
     res, off = w.db()
