@@ -22,7 +22,7 @@ The run takes hours of CPU.  It is resumable: records whose input digests
 match are kept, so an interrupted run continues where it stopped.
 
     python tests/golden/make_full_size.py [--threads N] [--only NAME ...]
-        [--queries I ...] [--out PATH]
+        [--queries I ...] [--out PATH] [--slices N]
 
 --queries limits the run to those query indices; --out writes the records to
 another file (for example on a machine with more cores), whose records
@@ -116,6 +116,8 @@ def main() -> None:
     ap.add_argument("--queries", nargs="*", type=int, default=None)
     ap.add_argument("--out", default=OUT)
     ap.add_argument("--merge", default=None)
+    ap.add_argument("--slices", type=int, default=1,
+                    help="compute each vector in this many slices of the database, printing each")
     args = ap.parse_args()
     if args.merge:
         merge(args.merge)
@@ -150,7 +152,20 @@ def main() -> None:
             if entries.get(key, {}).get("query_sha256") == q_sha:
                 continue
             t1 = time.time()
-            scores = orc.search(q, res, off, M, w.alpha, w.beta, nthreads=args.threads)
+            if args.slices > 1:
+                # the same per-subject scores, computed in slices of the
+                # database so that progress shows while a long query runs
+                n = len(off) - 1
+                parts = []
+                for x in range(args.slices):
+                    lo, hi = n * x // args.slices, n * (x + 1) // args.slices
+                    parts.append(orc.search_subset(q, res, off, np.arange(lo, hi, dtype=np.int64), M,
+                                                   w.alpha, w.beta, nthreads=args.threads))
+                    print(f"[golden] {name} q{i}: slice {x + 1}/{args.slices} "
+                          f"({time.time() - t1:.0f}s)", flush=True)
+                scores = np.concatenate(parts).astype(np.int32)
+            else:
+                scores = orc.search(q, res, off, M, w.alpha, w.beta, nthreads=args.threads)
             ts, ti = oracle.topk(scores, K)
             entries[key] = {
                 "qlen": len(q), "query_sha256": q_sha,
