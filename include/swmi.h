@@ -164,6 +164,30 @@ int sw_db_search(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring
 int sw_db_search_dev(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc,
                      int32_t *scores_dev, void *hip_stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the search of
+ * sw_db_search_dev with no allocation of any kind.  Every intermediate buffer
+ * (query profile, work lists, overflow list, counters, boundary columns, pass
+ * buffers) lives in one fixed device array of SW_NOALLOC_SCRATCH_BYTES per GPU,
+ * set up by sw_db_open and held until the process ends.
+ *   query_dev:  qlen residue codes in DEVICE memory on the database's device.
+ *               Codes are not checked (they are never read on the host): a code
+ *               >= alphabet scores 0 against every residue.
+ *   scores_dev: n_seqs int32 in DEVICE memory, caller's database order.
+ *   hip_stream: the work is enqueued on it and the call returns at once; NULL =
+ *               the library's stream, synchronised before returning.
+ * Scores equal sw_db_search's.  Launch grids are sized to fit the scratch, so
+ * long groups on a large database run at reduced occupancy; a query whose fixed
+ * state (profile, work lists, 8 bytes per subject of overflow list) or whose
+ * smallest launch does not fit fails with SW_EINVAL before any GPU work.
+ * Every call on one GPU shares that GPU's array and leaves its contents there:
+ * calls that overlap on one GPU (two databases, two streams, two threads) race
+ * and must be ordered by the caller.  sw_db_last_stats reports the plan and cell
+ * counts; times and the recompute count are -1 (nothing is read back). */
+#define SW_NOALLOC_SCRATCH_BYTES (256LL << 20)
+int sw_db_search_dev_noalloc(sw_db *db, const uint8_t *query_dev, int32_t qlen,
+                             const sw_scoring *sc, int32_t *scores_dev, void *hip_stream);
+
 /* The k best database sequences for one query (section III, stage iv: scores
  * sorted in descending order; equal scores by ascending database index).
  * top_scores[k], top_idx[k]; if k > n_seqs the tail is filled with -1. */

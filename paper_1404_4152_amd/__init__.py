@@ -100,6 +100,7 @@ SIGNATURES = {
     "sw_db_last_stats": (ctypes.c_int, [_vp, _P(sw_stats)]),
     "sw_db_search": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), _i32p, _vp]),
     "sw_db_search_dev": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), _vp, _vp]),
+    "sw_db_search_dev_noalloc": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _P(sw_scoring), _vp, _vp]),
     "sw_db_topk": (ctypes.c_int, [_vp, _u8p, ctypes.c_int32, _P(sw_scoring), ctypes.c_int32, _i32p,
                                   _i64p, _vp]),
     "sw_db_search_batch": (ctypes.c_int, [_vp, ctypes.c_int32, _u8p, _i64p, _P(sw_scoring),
@@ -230,6 +231,14 @@ def sw_db_search_dev(h, query, matrix, alpha, beta, scores_dev_ptr: int, stream=
     sc, keep = make_scoring(matrix, alpha, beta)
     return _check(lib().sw_db_search_dev(h, _ptr(q, ctypes.c_uint8), len(query), ctypes.byref(sc),
                                          ctypes.c_void_p(scores_dev_ptr), stream))
+
+
+def sw_db_search_dev_noalloc(h, query_dev_ptr: int, qlen: int, matrix, alpha, beta,
+                             scores_dev_ptr: int, stream=None):
+    sc, keep = make_scoring(matrix, alpha, beta)
+    return _check(lib().sw_db_search_dev_noalloc(h, ctypes.c_void_p(query_dev_ptr), int(qlen),
+                                                 ctypes.byref(sc), ctypes.c_void_p(scores_dev_ptr),
+                                                 stream))
 
 
 def sw_db_topk(h, query, matrix, alpha, beta, k, stream=None):

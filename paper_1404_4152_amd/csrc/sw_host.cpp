@@ -48,6 +48,8 @@
 
 using namespace swmi;
 
+static_assert(kNoAllocScratchBytes == (size_t)SW_NOALLOC_SCRATCH_BYTES, "scratch size");
+
 namespace {
 
 thread_local std::string g_err;
@@ -248,6 +250,7 @@ struct sw_db {
     bool fixed_cut = false;           // the caller fixed the split at open
     // device copies
     DevBuf d_res, d_off, d_codes, d_grp_base, d_grp_rows, d_grp_ids;
+    DevBuf d_long_ids;                // long_ids on the device (sw_db_search_dev_noalloc)
     // per-call workspaces (plain and batched searches)
     DevBuf w_stage, w_scores, w_counters, w_ovf, w_scr_inter, w_scr_intra, w_topk, w_top;
     HostBuf h_stage;
@@ -1578,6 +1581,7 @@ int db_create(int device, int32_t alphabet, std::unique_ptr<sw_db> &out) {
         db->arch = p.gcnArchName;
     }
     HIPX(prepare_kernels());
+    HIPX(noalloc_scratch_init(db->device));
     HIPX(hipStreamCreateWithFlags(&db->stream, hipStreamNonBlocking));
     HIPX(hipStreamCreateWithFlags(&db->aux, hipStreamNonBlocking));
     for (auto &e : db->ev) HIPX(hipEventCreate(&e));
@@ -1782,6 +1786,11 @@ int db_install(sw_db *db, const PackedView &v, hipStream_t st) {
         HIPX(hipMemcpyAsync(db->d_grp_ids.p, v.grp_ids, (size_t)ng * kGroup * 4,
                             hipMemcpyHostToDevice, st));
     }
+    if (v.n_long > 0) {
+        TRY(db->d_long_ids.reserve((size_t)v.n_long * 4));
+        HIPX(hipMemcpyAsync(db->d_long_ids.p, v.long_ids, (size_t)v.n_long * 4,
+                            hipMemcpyHostToDevice, st));
+    }
     HIPX(hipStreamSynchronize(st));
     return SW_OK;
 }
@@ -1889,6 +1898,162 @@ int sw_db_search_dev(sw_db *db, const uint8_t *query, int32_t qlen, const sw_sco
     const int64_t off[2] = {0, qlen};
     return run_search(db, 1, query, off, sc, 0, nullptr, nullptr, nullptr, scores_dev,
                       (hipStream_t)hip_stream);
+}
+
+// The search of sw_db_search_dev with every buffer in the device's fixed
+// scratch array: no hipMalloc, hipFree, pinned staging or host container.
+// The plan, the cut and the grids are worked out on the host from numbers
+// alone; the profile, query set and work lists are written by one setup
+// kernel; then the same pass as every other search runs.  Grids shrink until
+// their boundary and pass buffers fit what the fixed parts leave.
+int sw_db_search_dev_noalloc(sw_db *db, const uint8_t *query_dev, int32_t qlen,
+                             const sw_scoring *sc, int32_t *scores_dev, void *hip_stream) {
+    g_err.clear();
+    if (!db) return fail(SW_EINVAL, "db is NULL");
+    if (!query_dev) return fail(SW_EINVAL, "query_dev is NULL");
+    if (qlen < 1 || qlen > SW_MAX_LEN) return fail(SW_EINVAL, "query length %d not in 1..2^24", qlen);
+    if (!scores_dev && db->n_seqs > 0) return fail(SW_EINVAL, "scores_dev is NULL");
+    std::lock_guard<std::mutex> lk(db->mu);
+    TRY(busy(db));
+    TRY(validate_scoring(db, sc));
+    HIPX(hipSetDevice(db->device));
+    uint8_t *base = noalloc_scratch(db->device);
+    if (!base) return fail(SW_EDEVICE, "no-allocation scratch not initialised on device %d", db->device);
+    hipStream_t st = hip_stream ? (hipStream_t)hip_stream : db->stream;
+    const int64_t n = db->n_seqs;
+    if (n == 0) return SW_OK;
+
+    Plan plan = plan_for(db, qlen, sc->alpha);
+    plan.profile = SW_PROFILE_PAIR;   // the fixed scratch holds no query codes
+    const int W = plan.waves;
+    const int32_t mpad = (int32_t)round_up(qlen, kQPad);
+    const int resident = inter_max_grid(db->R, plan.tier, plan.strip, W) * W;
+    const int64_t g_cut = route_cut_groups(db, plan, &mpad, 1, resident);
+    const int64_t n_inter = (g_cut + W - 1) / W;
+    const int64_t n_long = (int64_t)db->long_ids.size() + (db->n_groups - g_cut) * kGroup;
+    const int Ti = intra_T_for(qlen);
+    const int pw = intra_per_wave(plan, n_long, db->cus);
+    const bool fused = fuse_ok(db, plan, Ti) && pw == 1;
+    const int per = fused ? W : kIntraWaves * pw;
+    const int64_t n_intra = (n_long + per - 1) / per;
+    Launch L = launch_config(db, plan, qlen, n_inter, n_intra, fused);
+    L.packed_long = !fused && per == 2 * kIntraWaves;
+    const int32_t rows_alloc = g_cut > 0 ? db->grp_rows[g_cut - 1] : 0;
+
+    // ---- fixed parts of the scratch ----
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += (size_t)round_up((int64_t)bytes, 256);
+        return at;
+    };
+    const size_t o_ctr = take(16);
+    const size_t o_qs = take(8 + 4 + 4 + 8);
+    const size_t o_prof = take((size_t)db->R * mpad);
+    const size_t o_it = take((size_t)n_inter * 8);
+    const size_t o_il = take((size_t)n_intra * (1 + per) * 4);
+    const size_t o_ovf = take((size_t)n * 8);
+    if (o + 512 > kNoAllocScratchBytes)
+        return fail(SW_EINVAL, "query of %d residues against %lld subjects needs %zu bytes of fixed "
+                    "state, more than the %zu-byte no-allocation scratch", qlen, (long long)n, o,
+                    kNoAllocScratchBytes);
+    // ---- grids within what is left ----
+    // what is left, less the alignment of the two regions below
+    const size_t rem = kNoAllocScratchBytes - o - 512;
+    const size_t per_slot = (size_t)intra_scratch_rows(db) * 8;        // one wave-per-pair wave
+    const size_t per_wg = (size_t)W * rows_alloc * 512;               // one lane-per-subject workgroup
+    int64_t grid_inter = 0, slots = 0;
+    const bool inter_launch = n_inter > 0 || L.fused_long;
+    if (inter_launch) {
+        if (fused) {
+            grid_inter = std::min<int64_t>(L.grid_inter, (int64_t)(rem / (per_wg + (size_t)W * per_slot)));
+            slots = grid_inter * W;
+        } else {
+            const size_t want_i = (size_t)std::max<int64_t>((int64_t)L.grid_long * kIntraWaves,
+                                                            L.grid_ovf) * per_slot;
+            const size_t keep_i = std::max(per_slot * kIntraWaves, std::min(want_i, rem / 4));
+            grid_inter = keep_i < rem ? std::min<int64_t>(L.grid_inter, (int64_t)((rem - keep_i) / per_wg)) : 0;
+            slots = (int64_t)((rem - (size_t)grid_inter * per_wg) / per_slot);
+        }
+    } else {
+        slots = (int64_t)(rem / per_slot);
+    }
+    const int64_t grid_long = std::min<int64_t>(L.grid_long, slots / kIntraWaves);
+    const int64_t grid_ovf = std::min<int64_t>(L.grid_ovf, slots);
+    if ((inter_launch && grid_inter < 1) || (n_intra > 0 && !fused && grid_long < 1) || grid_ovf < 1)
+        return fail(SW_EINVAL, "query of %d residues against this database does not fit the "
+                    "%zu-byte no-allocation scratch (groups of up to %d rows, subjects of up to "
+                    "%lld residues)", qlen, kNoAllocScratchBytes, rows_alloc, (long long)db->max_len);
+    L.grid_inter = (int)grid_inter;
+    L.grid_long = (int)grid_long;
+    L.grid_ovf = (int)grid_ovf;
+    const size_t o_b = take((size_t)grid_inter * per_wg);
+    const size_t o_i = take((size_t)std::max<int64_t>(slots, 1) * per_slot);
+    (void)o_i;
+
+    NoAllocSetup su{};
+    su.q = query_dev;
+    su.qlen = qlen;
+    su.mpad = mpad;
+    su.R = db->R;
+    su.A = db->alphabet;
+    std::memcpy(su.matrix, sc->matrix, (size_t)db->alphabet * db->alphabet);
+    su.alpha = sc->alpha;
+    su.beta = sc->beta;
+    su.prof = (int8_t *)(base + o_prof);
+    su.qp = (const int8_t **)(base + o_qs);
+    su.mpad_out = (int32_t *)(base + o_qs + 8);
+    su.qlen_out = (int32_t *)(base + o_qs + 12);
+    su.gap_out = (int32_t *)(base + o_qs + 16);
+    su.it_q = (int32_t *)(base + o_it);
+    su.it_g = su.it_q + n_inter;
+    su.n_inter = (int32_t)n_inter;
+    su.waves = W;
+    su.il_q = (int32_t *)(base + o_il);
+    su.il_ids = su.il_q + n_intra;
+    su.n_intra = (int32_t)n_intra;
+    su.per = per;
+    su.long_static = db->d_long_ids.as<int32_t>();
+    su.n_static = (int32_t)db->long_ids.size();
+    su.grp_ids = db->d_grp_ids.as<int32_t>();
+    su.g_cut = (int32_t)g_cut;
+    su.n_groups = db->n_groups;
+    HIPX(launch_noalloc_setup(su, st));
+
+    PassBufs pb;
+    pb.qs.qp = su.qp;
+    pb.qs.mpad = su.mpad_out;
+    pb.qs.qlen = su.qlen_out;
+    pb.qs.gap = su.gap_out;
+    pb.it_q = su.it_q;
+    pb.it_g = su.it_g;
+    pb.il_q = su.il_q;
+    pb.il_ids = su.il_ids;
+    pb.n_inter = n_inter;
+    pb.n_intra = n_intra;
+    pb.scores = scores_dev;
+    pb.ovf_q = (int32_t *)(base + o_ovf);
+    pb.ovf_id = pb.ovf_q + n;
+    pb.ovf_cap = n;
+    pb.counters = (int32_t *)(base + o_ctr);
+    pb.scr_inter = (uint32_t *)(base + o_b);
+    pb.scr_rows = rows_alloc;
+    pb.scr_intra = (int32_t *)(base + o_i);
+    TRY(enqueue_pass(db, L, pb, st));
+    if (!hip_stream) HIPX(hipStreamSynchronize(st));
+    sw_stats &stt = db->last;
+    stt = sw_stats{};
+    stt.cells = (int64_t)qlen * db->total_res;
+    stt.inter_cells = (int64_t)qlen * db->grp_res_prefix[g_cut];
+    stt.intra_pairs = (int64_t)db->long_ids.size() +
+                      std::max<int64_t>(0, n - (int64_t)db->long_ids.size() - g_cut * kGroup);
+    stt.kernel_ms = stt.total_ms = stt.inter_ms = stt.recompute_ms = stt.long_ms = -1;
+    stt.recomputed_pairs = -1;   // not read back (nothing is copied to the host)
+    stt.tier = plan.tier;
+    stt.strip = plan.strip;
+    stt.waves = W;
+    stt.fused_long = L.fused_long ? 1 : 0;
+    return SW_OK;
 }
 
 int sw_db_topk(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring *sc, int32_t k,

@@ -166,6 +166,36 @@ __host__ __device__ constexpr int align_pipe_lds_bytes(int R, int T, int P) {
 int align_pipe_plan(int R, int qlen, int *P_out);
 hipError_t launch_align(const AlignArgs &a, hipStream_t st);
 
+// Device scratch of the entry point that allocates nothing
+// (sw_db_search_dev_noalloc): one fixed array per GPU, held until the process
+// ends.  noalloc_scratch_init (called once per device by sw_db_open, with that
+// device current) takes the array's device address; noalloc_scratch returns it
+// (nullptr before initialisation).
+constexpr size_t kNoAllocScratchBytes = (size_t)256 << 20;
+hipError_t noalloc_scratch_init(int device);
+uint8_t *noalloc_scratch(int device);
+
+// Arguments of the kernel that writes the per-call state of one no-allocation
+// search into the scratch (see noalloc_setup_kernel).
+struct NoAllocSetup {
+    const uint8_t *q;            // query codes, device memory
+    int32_t qlen, mpad, R, A;
+    int8_t matrix[32 * 32];      // A x A, row = query residue
+    int32_t alpha, beta;
+    int8_t *prof;                // R x mpad
+    const int8_t **qp;           // one-slot query set
+    int32_t *mpad_out, *qlen_out, *gap_out;
+    int32_t *it_q, *it_g;        // lane-per-subject items
+    int32_t n_inter, waves;
+    int32_t *il_q, *il_ids;      // wave-per-pair items, `per` ids each
+    int32_t n_intra, per;
+    const int32_t *long_static;  // the database's long list (device)
+    int32_t n_static;
+    const int32_t *grp_ids;      // group slots (device), for groups g_cut..n_groups-1
+    int32_t g_cut, n_groups;
+};
+hipError_t launch_noalloc_setup(const NoAllocSetup &s, hipStream_t st);
+
 // Top-k by (score desc, index asc) over rows of `n` scores, `nq` rows.
 struct TopkWork {
     uint32_t *hist;      // nq * 256

@@ -2051,6 +2051,100 @@ hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t st) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch for sw_db_search_dev_noalloc (callers that cannot
+// allocate).  Host code never passes `scratch` itself to a kernel: in host
+// code the name is a host-side stand-in.  Its device address, one per GPU, is
+// taken once per device by noalloc_scratch_init and handed out by
+// noalloc_scratch.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device) return hipErrorInvalidDevice;   // the device must be current
+    uint8_t *ptr = nullptr;
+    e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = ptr;
+    return hipSuccess;
+}
+
+uint8_t *noalloc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
+
+// Per-call state of sw_db_search_dev_noalloc, written on the device: the
+// query profile (section III.B.2: row r holds the whole query's scores
+// against residue r; the pad row, columns past the query and query codes
+// outside the alphabet score 0), the one-slot query set, the work counters
+// and both work lists.  Lane-per-subject items: blocks of `waves` groups,
+// longest (highest) first.  Wave-per-pair items: the database's long list,
+// then every subject of groups g_cut.. in descending group order, `per` ids
+// per item (-1 past the end).
+__global__ void noalloc_setup_kernel(NoAllocSetup s) {
+    const int64_t tid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    const int64_t np = (int64_t)s.R * s.mpad;
+    for (int64_t e = tid; e < np; e += step) {
+        const int r = (int)(e / s.mpad), j = (int)(e - (int64_t)r * s.mpad);
+        int v = 0;
+        if (r < s.A && j < s.qlen) {
+            const int c = s.q[j];
+            if (c < s.A) v = s.matrix[c * s.A + r];
+        }
+        s.prof[e] = (int8_t)v;
+    }
+    if (tid == 0) {
+        s.qp[0] = s.prof;
+        s.mpad_out[0] = s.mpad;
+        s.qlen_out[0] = s.qlen;
+        s.gap_out[0] = s.alpha;
+        s.gap_out[1] = s.beta;
+    }
+    for (int64_t i = tid; i < s.n_inter; i += step) {
+        s.it_q[i] = 0;
+        s.it_g[i] = (int32_t)((s.n_inter - 1 - i) * s.waves);
+    }
+    const int64_t n_long = (int64_t)s.n_static + (int64_t)(s.n_groups - s.g_cut) * kGroup;
+    for (int64_t i = tid; i < (int64_t)s.n_intra * s.per; i += step) {
+        if (i % s.per == 0) s.il_q[i / s.per] = 0;
+        int32_t id = -1;
+        if (i < s.n_static) {
+            id = s.long_static[i];
+        } else if (i < n_long) {
+            const int64_t x = i - s.n_static;
+            const int64_t g = s.n_groups - 1 - x / kGroup;
+            id = s.grp_ids[g * kGroup + (kGroup - 1 - x % kGroup)];
+        }
+        s.il_ids[i] = id;
+    }
+}
+
+hipError_t launch_noalloc_setup(const NoAllocSetup &s, hipStream_t st) {
+    const int64_t work = std::max<int64_t>((int64_t)s.R * s.mpad,
+                                           std::max<int64_t>(s.n_inter, (int64_t)s.n_intra * s.per));
+    int64_t blocks = (work + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(noalloc_setup_kernel, dim3((unsigned)blocks), dim3(256), 0, st, s);
+    return hipGetLastError();
+}
+
 __global__ void topk_init(int32_t *state, uint32_t *hist, int32_t k) {
     const int q = blockIdx.x;
     for (int b = threadIdx.x; b < 256; b += blockDim.x) hist[q * 256 + b] = 0;
