@@ -1434,7 +1434,7 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
         // The last pass takes the fewest columns per lane that hold its
         // columns: every step costs all of a lane's columns, used or not.
         const int rem = qlen - (npass - 1) * PW;
-        const int tl = T == 16 ? (rem <= 256 ? 4 : rem <= 512 ? 8 : 16) : T;
+        const int tl = T == 16 ? (rem <= 256 ? 4 : rem <= 512 ? 8 : rem <= 768 ? 12 : 16) : T;
         const int8_t *qp = a.qs.qp[q];
         const int alpha = a.qs.gap[2 * q];
         const LaneFrame ops(min(alpha, kFrameMaxAlpha), a.qs.gap[2 * q + 1]);
@@ -1463,6 +1463,11 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
                 if (last && tl == 8) {
                     if (has_in) intra2_pass<8, true, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
                     else intra2_pass<8, false, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    continue;
+                }
+                if (last && tl == 12) {
+                    if (has_in) intra2_pass<12, true, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
+                    else intra2_pass<12, false, false>(a, ops, prof, rs, wsc, ring, sa, sb, na, nb, pad, best);
                     continue;
                 }
             }

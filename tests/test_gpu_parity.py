@@ -239,7 +239,8 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     """The packed fp16 wave-per-pair kernel (every subject on the long list,
     9,000 pairs) with queries of one, two and three passes of 64 x T columns:
     the pass boundary is stored as true values and re-offset on the way in.
-    The last pass narrows to 4 columns per lane (1,100, 2,100) or 8 (1,400).
+    The last pass narrows to 4 columns per lane (1,100, 2,100), 8 (1,400) or
+    12 (1,700: 1,024 columns, then 676 at 12 per lane).
     Subjects span several 64-row feed blocks and 32-step frame periods;
     alpha 29 flags every half (ceiling 0) and the recompute keeps it exact."""
     rng = np.random.Generator(np.random.PCG64(400 + alpha))
@@ -248,7 +249,7 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     db = swmi.Database(res, off, 20, long_threshold=1)
     try:
         db.set_opts(tier=1)
-        for L in [5, 300, 1100, 1400, 2100]:
+        for L in [5, 300, 1100, 1400, 1700, 2100]:
             q = sd.random_residues(rng, L)
             print(f"packed wave-per-pair alpha={alpha} qlen={L}", flush=True)
             exp = orc.search(q, res, off, M, alpha, beta)
@@ -263,12 +264,13 @@ def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
 
 def test_packed_wave_per_pair_batch_mixed_lengths(swmi, orc):
     """A batch whose longest query sets 16 columns per lane for the packed
-    kernel: shorter queries run their single (or last) pass at 4 or 8
-    columns per lane, longer ones a narrowed last pass after full ones."""
+    kernel: shorter queries run their single (or last) pass at 4, 8 or 12
+    columns per lane (600 at 12), longer ones a narrowed last pass after
+    full ones."""
     rng = np.random.Generator(np.random.PCG64(812))
     M = sd.blosum_style_matrix()
     res, off = random_db(rng, 9000, 20, 0, 180, zero_every=83)
-    qs = [sd.random_residues(rng, L) for L in (40, 300, 700, 1100, 1400)]
+    qs = [sd.random_residues(rng, L) for L in (40, 300, 600, 700, 1100, 1400)]
     db = swmi.Database(res, off, 20, long_threshold=1)
     try:
         db.set_opts(tier=1)
