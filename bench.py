@@ -200,6 +200,7 @@ def run_plain(args, swmi, sd, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     align = None if args.no_align else run_align(args, swmi, db, w, res, off, queries, M)
+    high_alpha = run_high_alpha(args, swmi, db, w, res, queries, M, sptr, torch)
     db.close()
     gcups = cells_step * args.steps / dt / 1e9
     st0 = all_sts[0]
@@ -232,6 +233,7 @@ def run_plain(args, swmi, sd, torch):
     }
     if align:
         out["align_topk"] = align
+    out["high_alpha"] = high_alpha
     if inter:
         # One launch of the lane-per-subject kernel per query.  Its cells: the
         # lane-per-subject cells, plus the long list's when that ran inside the
@@ -360,6 +362,29 @@ def run_profile_ab(args, swmi, sd, torch):
     return {"workload": w.name, "plan": "fp16, strip 32, 4 waves, the database's own routing",
             "timed": "device time of the whole search (kernel_ms)",
             "rows": rows, "score_vs_pair_total_time": round(tot_p / tot_s, 4)}
+
+
+def run_high_alpha(args, swmi, db, w, res, queries, M, sptr, torch):
+    """The same database and planner at a gap extension past the fp16 frame's
+    range (alpha 60, beta 80: the int16 tier), against alpha 2 for the same
+    three queries (short, middle, long), one search each after a warm-up."""
+    pick = [queries[0], queries[len(queries) // 2], queries[-1]]
+    cells = sum(len(q) for q in pick) * int(len(res))
+    out = {"queries": [len(q) for q in pick]}
+    for name, (a, b) in (("alpha_2", (w.alpha, w.beta)), ("alpha_60", (60, 80))):
+        swmi.sw_db_topk(db.h, pick[0], M, a, b, args.k, stream=sptr)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        tiers = set()
+        for q in pick:
+            swmi.sw_db_topk(db.h, q, M, a, b, args.k, stream=sptr)
+            tiers.add(db.stats()["tier"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out[name] = {"gcups": round(cells / dt / 1e9, 1), "tiers": sorted(tiers)}
+    log(f"[bench] alpha 60 (int16 tier): {out['alpha_60']['gcups']} GCUPS against "
+        f"{out['alpha_2']['gcups']} at alpha 2")
+    return out
 
 
 def run_align(args, swmi, db, w, res, off, queries, M):

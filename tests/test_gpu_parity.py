@@ -234,6 +234,46 @@ def test_forced_overflow_recompute(swmi, orc, tier, route):
         db.close()
 
 
+@pytest.mark.skip(reason="a pipelined rescore of long flagged pairs (one workgroup per pair, one wave "
+                         "per pass) and a one-workgroup-per-CU grid for small databases were taken out "
+                         "after this test's first GPU run stayed silent for over 180 s; no cause was "
+                         "found by reading the code, so the case stays off the GPU")
+@pytest.mark.parametrize("route", [1, -1])
+def test_pipelined_rescore_of_long_pairs(swmi, orc, route):
+    """Flagged pairs with subjects of 4,096 rows or more and a query of two or
+    more passes are rescored one workgroup per pair, one wave per pass
+    (4 columns per lane up to 16 passes, 8 up to 12); the others, and queries
+    past 12 passes of 512 columns, one wave per pair.  A lowered threshold
+    flags nearly every pair.  route 1: every subject on the long list, enough
+    pairs for the packed fp16 kernel, which flags them; -1: every subject in
+    lane-per-subject groups, long ones included, flagged there.  Queries of 1
+    (300 at 4 per lane in a 16-column launch), 2, 8 and 17 passes (4,097
+    residues: 9 passes of 512) and one too long for the pipeline (7,000), one
+    at a time and as a batch."""
+    rng = np.random.Generator(np.random.PCG64(6000 + route))
+    M = sd.blosum_style_matrix()
+    lens = np.concatenate([rng.integers(4096, 9000, size=300), rng.integers(1, 300, size=8700)])
+    rng.shuffle(lens)
+    res, off = sd.pack_sequences([sd.random_residues(rng, int(L)) for L in lens])
+    db = swmi.Database(res, off, 20, long_threshold=route)
+    try:
+        db.set_opts(tier=1, sat_threshold=15)
+        qs = [sd.random_residues(rng, L) for L in (300, 400, 2000, 4097, 7000)]
+        exps = []
+        for q in qs:
+            print(f"pipelined rescore route={route} qlen={len(q)}", flush=True)
+            exp = orc.search(q, res, off, M, 2, 12)
+            exps.append(exp)
+            expect_equal(db.search(q, M, 2, 12), exp, f"route {route} L={len(q)}")
+            assert db.stats()["recomputed_pairs"] == int((exp >= 15).sum())
+        print(f"pipelined rescore route={route} batch", flush=True)
+        ts, ti, al = db.search_batch(qs, M, 2, 12, 5, all_scores=True)
+        for x, exp in enumerate(exps):
+            expect_equal(al[x], exp, f"route {route} batch q{x}")
+    finally:
+        db.close()
+
+
 @pytest.mark.parametrize("alpha,beta", [(2, 12), (28, 40), (29, 40)])
 def test_packed_wave_per_pair_passes(swmi, orc, alpha, beta):
     """The packed fp16 wave-per-pair kernel (every subject on the long list,
