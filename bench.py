@@ -200,7 +200,8 @@ def run_plain(args, swmi, sd, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     align = None if args.no_align else run_align(args, swmi, db, w, res, off, queries, M)
-    high_alpha = run_high_alpha(args, swmi, db, w, res, queries, M, sptr, torch)
+    high_alpha = None if args.no_high_alpha else run_high_alpha(args, swmi, db, w, res, queries, M,
+                                                                 sptr, torch)
     db.close()
     gcups = cells_step * args.steps / dt / 1e9
     st0 = all_sts[0]
@@ -233,7 +234,8 @@ def run_plain(args, swmi, sd, torch):
     }
     if align:
         out["align_topk"] = align
-    out["high_alpha"] = high_alpha
+    if high_alpha:
+        out["high_alpha"] = high_alpha
     if inter:
         # One launch of the lane-per-subject kernel per query.  Its cells: the
         # lane-per-subject cells, plus the long list's when that ran inside the
@@ -261,6 +263,26 @@ def run_plain(args, swmi, sd, torch):
                 "why_frac_can_exceed_1": "the count of 8 takes alpha off E and F at every cell; "
                                          "the frame form stores values offset by alpha per row "
                                          "and per column within groups of 4, so it needs 5.75"}}
+    fused_only = [s for s in all_sts
+                  if s["inter_cells"] == 0 and s["fused_long"] and s["inter_ms"] > 0]
+    if not inter and fused_only:
+        # too few subjects to fill the chip lane-per-subject (plain_small):
+        # every pair is an int32 wave-per-pair item inside the lane-per-subject
+        # kernel's launch; priced at the textbook 8 int32 ops per cell against
+        # the 32-bit VALU peak
+        avg_ms = sum(s["inter_ms"] for s in fused_only) / len(fused_only)
+        cells_launch = sum(s["cells"] for s in fused_only) / len(fused_only)
+        peak = PEAK_LANE_OPS / 1e12
+        achieved = OPS_PER_CELL_TEXTBOOK * cells_launch / (avg_ms / 1e3) / 1e12
+        out["roofline"] = {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 2),
+            "unit": "Tops/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "traffic_unit": "bytes per launch",
+            "kernel": "inter_kernel (long list only: int32 wave-per-pair items)",
+            "ops_per_cell": OPS_PER_CELL_TEXTBOOK, "cells_per_launch": round(cells_launch),
+            "avg_launch_ms": round(avg_ms, 3),
+            "basis": "int32 VALU lane-ops at the textbook 8 per cell over the 32-bit VALU peak; "
+                     "a launch this small is bound by its latency, not by either peak"}
     longs = [s for s in all_sts if s["inter_cells"] == 0 and s["long_ms"] > 0]
     if not inter and longs:
         # every subject on the wave-per-pair kernel (long_tail): its own launch,
@@ -591,6 +613,8 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-align", action="store_true")
     ap.add_argument("--no-streamed", action="store_true")
+    ap.add_argument("--no-high-alpha", action="store_true",
+                    help="skip the alpha 60 (int16 tier) searches after the timed steps")
     ap.add_argument("--profile-ab", action="store_true",
                     help="only the pair- vs score-profile A/B on plain_scale's query lengths")
     ap.add_argument("--serve-seconds", type=float, default=4.0)

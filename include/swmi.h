@@ -125,7 +125,8 @@ typedef struct sw_stats {
     double  recompute_ms;     /* device time of the exact int32 recompute of flagged pairs
                                  (-1 when the work ran as a graph) */
     double  long_ms;          /* device time of the wave-per-pair kernel when it ran alone
-                                 (no lane-per-subject work in the call); -1 otherwise */
+                                 (no lane-per-subject work in the call, not fused); -1
+                                 otherwise (a fused long list is timed in inter_ms) */
     int32_t profile;          /* SW_PROFILE_* of the lane-per-subject kernel */
     int32_t reserved0;
 } sw_stats;
@@ -249,8 +250,12 @@ int sw_db_align(sw_db *db, const uint8_t *query, int32_t qlen, const sw_scoring 
 
 /* Run the autotuner: for each query-length bucket of the given lengths, time
  * every candidate plan on a sample of this database's blocks, re-time the two
- * fastest on the whole database (best of two runs) and keep the faster.  If
- * cache_path is non-NULL the table is read from / written to that JSON file.
+ * fastest on the whole database (best of two runs) and keep the faster.  With
+ * more than one length, also time the distinct winners and the default plan on
+ * a batch of up to 32 of the lengths (a sample of the blocks) and keep the
+ * fastest as the plan of every launch of several queries (sw_db_search_batch;
+ * bucket -1 in the cache).  If cache_path is non-NULL the table is read from /
+ * written to that JSON file.
  * No passage of the paper defines it; it plays the part of the paper's
  * empirical choices of thread count and schedule (section III.A) and of the
  * score profile's depth (section III.B.3). */

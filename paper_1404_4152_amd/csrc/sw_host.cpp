@@ -166,6 +166,9 @@ int qlen_bucket(int64_t qlen) {
     return b;
 }
 
+// The autotuner's entry for launches of several queries at once.
+constexpr int kBatchBucket = -1;
+
 // Work item lists of one device pass, built on the host.
 struct Items {
     std::vector<int32_t> inter_q, inter_g;   // lane-per-subject: (slot, first group of block)
@@ -295,9 +298,12 @@ int validate_query(const sw_db *db, const uint8_t *q, int64_t qlen) {
 }
 
 // alpha: the gap extension of the search (0 when it varies per query).
-Plan plan_for(const sw_db *db, int64_t max_qlen, int alpha) {
+// nq: queries in the launch; a launch of several takes the autotuner's batch
+// entry when it has one.
+Plan plan_for(const sw_db *db, int64_t max_qlen, int alpha, int32_t nq = 1) {
     Plan p;
-    auto it = db->tuned.find(qlen_bucket(max_qlen));
+    auto it = nq > 1 ? db->tuned.find(kBatchBucket) : db->tuned.end();
+    if (it == db->tuned.end()) it = db->tuned.find(qlen_bucket(max_qlen));
     if (it != db->tuned.end()) p = it->second;
     // The fp16 tier's ceiling falls by 36 per unit of alpha (frame offsets);
     // past kFrameMaxAlpha the int16 tier flags far fewer lanes.
@@ -729,7 +735,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     if ((int64_t)nq * db->n_seqs > ((int64_t)1 << 40)) return fail(SW_EINVAL, "batch too large");
     HIPX(hipSetDevice(db->device));
     hipStream_t st = user_stream ? user_stream : db->stream;
-    const Plan plan = plan_for(db, max_qlen, sc->alpha);
+    const Plan plan = plan_for(db, max_qlen, sc->alpha, nq);
     const int64_t n = db->n_seqs;
 
     std::vector<int32_t> slots(nq);
@@ -909,8 +915,10 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     if (!graphed) {
         HIPX(hipEventElapsedTime(&ms_i, db->ev[0], db->ev[1]));
         HIPX(hipEventElapsedTime(&ms_r, db->ev[4], db->ev[2]));
-        // the wave-per-pair kernel alone on the stream, between the two
-        if (n_inter == 0 && n_intra > 0) HIPX(hipEventElapsedTime(&ms_l, db->ev[1], db->ev[4]));
+        // the wave-per-pair kernel alone on the stream, between the two (a
+        // long list fused into the lane-per-subject launch is timed in ms_i)
+        if (n_inter == 0 && n_intra > 0 && !L.fused_long)
+            HIPX(hipEventElapsedTime(&ms_l, db->ev[1], db->ev[4]));
     }
     sw_stats &s = db->last;
     s = sw_stats{};
@@ -1072,6 +1080,67 @@ int autotune(sw_db *db, const sw_scoring *sc, const int32_t *qlens, int32_t n_ql
         }
         db->tuned[b] = best_plan;
         best_gcups[b] = best;
+    }
+    // A launch of several queries runs one plan for all of them, and the
+    // winner for its longest query's bucket can be a poor choice for the mix.
+    // Time the distinct bucket winners and the default plan on a batch of up
+    // to 32 of the given lengths (every stride-th block, at most about 4e12
+    // cells a run) and keep the fastest as the batch entry; with a single
+    // candidate, nothing is timed.
+    if (n_qlens > 1 && !best_gcups.empty()) {
+        std::vector<Plan> cands{Plan{}};
+        for (const auto &kv : db->tuned) {
+            if (kv.first == kBatchBucket) continue;
+            bool seen = false;
+            for (const Plan &c : cands)
+                seen = seen || (c.tier == kv.second.tier && c.strip == kv.second.strip &&
+                                c.waves == kv.second.waves);
+            if (!seen && inter_lds_bytes(db->R, kv.second.strip) <= 150 * 1024)
+                cands.push_back(kv.second);
+        }
+        const int32_t m_max = std::min<int32_t>(n_qlens, 32);
+        const double cell_cap = 4e12 * (double)stride / (double)std::max<int64_t>(1, db->total_res);
+        int32_t m = 0;
+        std::vector<int64_t> off(1, 0);
+        std::vector<uint8_t> qs;
+        for (int32_t x = 0; x < m_max && (m < 2 || (double)qs.size() < cell_cap); ++x, ++m) {
+            const int64_t L = std::max(1, std::min(qlens[(int64_t)x * n_qlens / m_max], SW_MAX_LEN));
+            for (int64_t j = 0; j < L; ++j) {
+                lcg = lcg * 1664525u + 1013904223u;
+                qs.push_back((uint8_t)((lcg >> 16) % (uint32_t)db->alphabet));
+            }
+            off.push_back((int64_t)qs.size());
+        }
+        const int32_t longest = *std::max_element(qlens, qlens + n_qlens);
+        const int lb = qlen_bucket(std::max(1, std::min(longest, SW_MAX_LEN)));
+        double best = best_gcups.count(lb) ? best_gcups[lb] : 0.0;
+        Plan best_plan = cands.size() == 1 ? cands[0] : db->tuned.at(lb);
+        if (cands.size() > 1) best = -1;
+        for (size_t ci = 0; cands.size() > 1 && ci < cands.size(); ++ci) {
+            const Plan &cand = cands[ci];
+            sw_search_opts o{};
+            o.tier = cand.tier;
+            o.strip = cand.strip;
+            o.waves = cand.waves;
+            db->opts = o;
+            double ms = 1e30;
+            for (int rep = 0; rep <= 2; ++rep) {
+                const int rc = run_search(db, m, qs.data(), off.data(), sc, 0, nullptr, nullptr,
+                                          nullptr, nullptr, nullptr, stride);
+                if (rc != SW_OK) {
+                    db->opts = saved;
+                    return rc;
+                }
+                if (rep > 0) ms = std::min(ms, (double)db->last.inter_ms);
+            }
+            const double gc = (double)db->last.inter_cells / stride / (ms * 1e6);
+            if (gc > best) {
+                best = gc;
+                best_plan = cand;
+            }
+        }
+        db->tuned[kBatchBucket] = best_plan;
+        best_gcups[kBatchBucket] = best;
     }
     db->opts = saved;
     if (cache_path) TRY(write_cache(db, cache_path, best_gcups));

@@ -1036,11 +1036,12 @@ __device__ __forceinline__ void intra_row(int (&H)[T], int (&E)[T], const uint2 
     fout = f;
 }
 
-// One wave-per-pair item: the W waves of the workgroup share the query's
-// profile (built per pass in `lds`) and each aligns one subject of the item.
-// Every wave reaches every barrier (waves without a subject skip the rows).
+// One query against one subject per wave (id < 0: none): the W waves of the
+// workgroup share the query's profile (built per pass in `lds`).  Every wave
+// reaches every barrier (waves without a subject skip the rows); q must be
+// the same for the whole workgroup.
 template <int T, int W>
-__device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t *lds,
+__device__ __forceinline__ void intra_pair(const IntraArgs &a, int q, int id, uint32_t *lds,
                                            int32_t *wsc) {
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // int16 per profile row (padded)
@@ -1049,8 +1050,6 @@ __device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t 
     const int w = threadIdx.x >> 6;
     uint32_t *ring = lds + (a.R * RS * 2 + w * kRing2Bytes) / 4;   // after the profile
     const int pad = a.R - 1;
-    const int q = a.item_q[it];
-    const int id = a.item_ids[(size_t)it * W + w];
     const int64_t n64 = id >= 0 ? a.off[id + 1] - a.off[id] : 0;
     const int n = (int)n64;
     const uint8_t *s = id >= 0 ? a.res + a.off[id] : a.res;
@@ -1149,6 +1148,14 @@ __device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t 
     }
 }
 
+// One wave-per-pair item: one subject per wave, all against the item's query.
+template <int T, int W>
+__device__ __forceinline__ void intra_item(const IntraArgs &a, int it, uint32_t *lds,
+                                           int32_t *wsc) {
+    const int w = threadIdx.x >> 6;
+    intra_pair<T, W>(a, a.item_q[it], a.item_ids[(size_t)it * W + w], lds, wsc);
+}
+
 template <int T, int W>
 __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
@@ -1161,6 +1168,9 @@ __global__ void __launch_bounds__(W * 64) intra_kernel(IntraArgs a) {
         __syncthreads();
         const int it = s_item;
         if (it >= n_items) break;
+        // one wave per workgroup (the recompute list): skip entries the packed
+        // kernel has already recomputed (id -1) without building a profile
+        if (W == 1 && a.item_ids[it] < 0) continue;
         intra_item<T, W>(a, it, lds, wsc);   // its first barrier orders the read of s_item
     }
 }
@@ -1406,7 +1416,8 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
     constexpr int RS = PW + 8;          // fp16 entries per profile row (padded)
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint16_t *prof = (uint16_t *)lds;
-    __shared__ int s_item;
+    __shared__ int s_item, s_nflag;
+    __shared__ int s_flag[2 * W];
 
     const int lane = threadIdx.x & 63;
     const int w = threadIdx.x >> 6;
@@ -1416,7 +1427,10 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
     const int n_items = a.n_items_dev ? *a.n_items_dev : a.n_items;
 
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(a.counter, 1);
+        if (threadIdx.x == 0) {
+            s_item = atomicAdd(a.counter, 1);
+            s_nflag = 0;
+        }
         __syncthreads();
         const int it = s_item;
         if (it >= n_items) break;
@@ -1484,6 +1498,10 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
             const h2 other = as_v<h2>((uint32_t)__shfl_xor((int)as_u(best), o, 64));
             best = __builtin_elementwise_maximum(best, other);
         }
+        // A flagged half is recomputed exactly (int32) by this workgroup at
+        // once, one subject per wave, while the other workgroups go on with
+        // the queue; it is still counted in the recompute list, with id -1
+        // so that the recompute launch after this one skips it.
         if (lane == 0) {
             const int ids[2] = {id_a, id_b};
 #pragma unroll
@@ -1491,16 +1509,25 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
                 if (ids[half] < 0) continue;
                 bool flag;
                 const int v = L::value(best, half, thr, &flag);
-                a.scores[(size_t)q * a.n_seqs + ids[half]] = v;
-                if (flag) {
-                    const int pos = atomicAdd(a.ovf_count, 1);
-                    if (pos < a.ovf_cap) {
-                        a.ovf_q[pos] = q;
-                        a.ovf_id[pos] = ids[half];
-                    }
+                if (!flag) {
+                    a.scores[(size_t)q * a.n_seqs + ids[half]] = v;
+                    continue;
+                }
+                s_flag[atomicAdd(&s_nflag, 1)] = ids[half];
+                const int pos = atomicAdd(a.ovf_count, 1);
+                if (pos < a.ovf_cap) {
+                    a.ovf_q[pos] = q;
+                    a.ovf_id[pos] = -1;
                 }
             }
         }
+        __syncthreads();
+        const int nflag = s_nflag;      // the same in every wave: the loop below meets
+        for (int b = 0; b < nflag; b += W)   // the same barriers in all of them
+            intra_pair<T, W>(a, q, b + w < nflag ? s_flag[b + w] : -1, lds, wsc);
+        // every wave has read s_nflag and s_flag before thread 0 resets the
+        // count for the next item
+        __syncthreads();
     }
 }
 

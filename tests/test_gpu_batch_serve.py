@@ -78,11 +78,20 @@ def test_autotune_and_cache(swmi, orc, tmp_path):
     try:
         swmi.sw_db_autotune(db.h, M, 2, 12, [100, 600], path)
         text = json.load(open(path))
-        assert len(text["entries"]) == 2
+        # buckets of 100 and 600 residues, and the batch entry (bucket -1)
+        assert sorted(e["bucket"] for e in text["entries"]) == [-1, 1, 4]
         for e in text["entries"]:
             assert e["tier"] in (1, 2) and e["strip"] in (16, 32, 64) and e["gcups"] > 0
         q = sd.random_residues(rng, 600)
         assert np.array_equal(db.search(q, M, 2, 12), orc.search(q, res, off, M, 2, 12))
+        # a launch of several queries runs the batch entry's plan
+        batch = next(e for e in text["entries"] if e["bucket"] == -1)
+        qs = [sd.random_residues(rng, L) for L in (100, 600, 333)]
+        ts, ti, al = db.search_batch(qs, M, 2, 12, 5, all_scores=True)
+        st = db.stats()
+        assert (st["tier"], st["strip"], st["waves"]) == (batch["tier"], batch["strip"], batch["waves"])
+        for x, qx in enumerate(qs):
+            assert np.array_equal(al[x], orc.search(qx, res, off, M, 2, 12))
     finally:
         db.close()
     db = swmi.Database(res, off, 20, long_threshold=-1)
