@@ -234,6 +234,46 @@ def test_forced_overflow_recompute(swmi, orc, tier, route):
         db.close()
 
 
+def test_packed_in_kernel_recompute_batch_graph(swmi, orc):
+    """The packed wave-per-pair kernel recomputes the halves it flags in int32
+    inside its own launch, one subject per wave of the flagging workgroup, in
+    rounds of W when an item flags more than W.  Every subject on the long
+    list (9,000 pairs per query: the packed kernel), a lowered threshold that
+    flags some halves of most items and every half of some, planted copies of
+    the first batch's queries above the fp16 ceiling, queries of one and two
+    passes, as a captured batch replayed with other queries of the same
+    lengths, eager searches between."""
+    rng = np.random.Generator(np.random.PCG64(808))
+    M = sd.blosum_style_matrix()
+    lens_q = (90, 300, 700, 1100)
+    batches = [[sd.random_residues(rng, L) for L in lens_q] for _ in range(3)]
+    res, off = random_db(rng, 9000, 20, 0, 260, zero_every=53)
+    q700, q1100 = batches[0][2], batches[0][3]
+    res, off = sd.rebuild_db(res, off, {100: q700.copy(), 101: sd.mutate(rng, q700, 0.9),
+                                        4000: q1100[:500].copy()})
+    db = swmi.Database(res, off, 20, long_threshold=1)
+    try:
+        db.set_opts(tier=1, sat_threshold=30)
+        for rep, qs in enumerate(batches):
+            print(f"in-kernel recompute rep {rep}", flush=True)
+            exps = [orc.search(q, res, off, M, 2, 12) for q in qs]
+            if rep == 0:
+                assert exps[2][100] >= 1848 and exps[3][4000] >= 1848
+            ts, ti, al = db.search_batch(qs, M, 2, 12, 10, all_scores=True)
+            st = db.stats()
+            assert st["inter_cells"] == 0 and st["intra_pairs"] == 9000 * len(qs)
+            assert st["recomputed_pairs"] == sum(int((e >= 30).sum()) for e in exps)
+            assert st["graphed"] == (1 if rep > 0 else st["graphed"])
+            for x, e in enumerate(exps):
+                expect_equal(al[x], e, f"rep {rep} q{x}")
+                es, ei = oracle.topk(e, 10)
+                assert np.array_equal(ts[x], es) and np.array_equal(ti[x], ei)
+            q0 = sd.random_residues(rng, 150)     # eager work between replays
+            expect_equal(db.search(q0, M, 2, 12), orc.search(q0, res, off, M, 2, 12), f"eager {rep}")
+    finally:
+        db.close()
+
+
 @pytest.mark.skip(reason="a pipelined rescore of long flagged pairs (one workgroup per pair, one wave "
                          "per pass) and a one-workgroup-per-CU grid for small databases were taken out "
                          "after this test's first GPU run stayed silent for over 180 s; no cause was "
