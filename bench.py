@@ -231,6 +231,10 @@ def run_plain(args, swmi, sd, torch):
                                        max(args.steps, 1), 3),
         "recompute_share": round(sum(max(s["recompute_ms"], 0.0) for s in all_sts) /
                                  max(sum(s["kernel_ms"] for s in all_sts), 1e-9), 5),
+        # cells evaluated beyond the real ones: groups padded to their longest
+        # subject, queries to the strip or to the wave-per-pair pass width
+        "padding": round(sum(s["padded_cells"] for s in all_sts) /
+                         max(sum(s["cells"] for s in all_sts), 1) - 1, 4),
     }
     if align:
         out["align_topk"] = align

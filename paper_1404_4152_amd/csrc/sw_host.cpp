@@ -182,8 +182,17 @@ struct Items {
 // exact int32 alignment otherwise (and in the int16 plan).  Below that count
 // the longest pair sets the makespan either way and the int32 kernel measured
 // as fast or faster (one query against 2M subjects: ~2,200 long pairs).
-int intra_per_wave(const Plan &plan, int64_t pairs, int cus) {
-    return plan.tier == TIER_F16X2 && pairs >= 32LL * cus ? 2 : 1;
+// all_long: the launch has no lane-per-subject work (a small database, or a
+// server pass at the long list's scan position); ti: its columns per lane.
+int intra_per_wave(const Plan &plan, int64_t pairs, int cus, bool all_long = false, int ti = 16) {
+    if (plan.tier != TIER_F16X2) return 1;
+    if (pairs >= 32LL * cus) return 2;
+    // Alone in its launch, the packed kernel halves the waves of a small long
+    // list.  On databases of 100-6,000 subjects of 20-2,000 residues it took
+    // 7-18% less time per search than the int32 long list, except at 8
+    // columns per lane below about 1,500 pairs (up to 7% more).
+    if (all_long && pairs > 0 && (ti != 8 || pairs >= 6LL * cus)) return 2;
+    return 1;
 }
 
 // Whether an int32 long list runs inside the lane-per-subject kernel's own
@@ -422,7 +431,9 @@ void build_items(const sw_db *db, const Plan &plan, const std::vector<int32_t> &
     it.fused = false;
     if (!with_long) return;
     const int64_t nlong = (int64_t)long_ids.size();
-    const int pw = intra_per_wave(plan, nlong * (int64_t)slots.size(), db->cus);
+    const int64_t max_q = qlen.empty() ? 1 : *std::max_element(qlen.begin(), qlen.end());
+    const int pw = intra_per_wave(plan, nlong * (int64_t)slots.size(), db->cus, v.empty(),
+                                  intra_T_for(max_q));
     it.fused = fuse && pw == 1;
     const int per = it.fused ? W : kIntraWaves * pw;
     it.per_item = per;
@@ -646,7 +657,10 @@ int enqueue_pass(const sw_db *db, const Launch &L, const PassBufs &b, hipStream_
     }
     if (fork) HIPX(hipStreamWaitEvent(st, db->join, 0));
     if (ev_r) HIPX(hipEventRecord(ev_r, st));
-    if (b.n_inter > 0 || (packed_long && b.n_intra > 0)) {
+    // Only the lane-per-subject kernel leaves flagged pairs for this launch:
+    // the packed wave-per-pair kernel recomputes its own, and the int32 one
+    // flags nothing.
+    if (b.n_inter > 0) {
         IntraArgs oa = ia;
         oa.item_q = b.ovf_q;
         oa.item_ids = b.ovf_id;
@@ -2001,7 +2015,7 @@ int sw_db_search_dev_noalloc(sw_db *db, const uint8_t *query_dev, int32_t qlen,
     const int64_t n_inter = (g_cut + W - 1) / W;
     const int64_t n_long = (int64_t)db->long_ids.size() + (db->n_groups - g_cut) * kGroup;
     const int Ti = intra_T_for(qlen);
-    const int pw = intra_per_wave(plan, n_long, db->cus);
+    const int pw = intra_per_wave(plan, n_long, db->cus, n_inter == 0, Ti);
     const bool fused = fuse_ok(db, plan, Ti) && pw == 1;
     const int per = fused ? W : kIntraWaves * pw;
     const int64_t n_intra = (n_long + per - 1) / per;

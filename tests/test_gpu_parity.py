@@ -234,6 +234,37 @@ def test_forced_overflow_recompute(swmi, orc, tier, route):
         db.close()
 
 
+@pytest.mark.parametrize("n", [300, 1700])
+def test_small_database_all_long_list(swmi, orc, n):
+    """A database too small to fill the chip lane-per-subject runs all of it as
+    the long list.  Alone in its launch, the packed fp16 kernel takes it
+    (two subjects per wave), except at 8 columns per lane (queries of 257-512
+    residues) below 1,536 pairs, where the int32 long list inside the
+    lane-per-subject kernel does; with a lowered threshold the packed kernel
+    recomputes what it flags itself."""
+    rng = np.random.Generator(np.random.PCG64(1700 + n))
+    M = sd.blosum_style_matrix()
+    lens = np.clip(np.round(rng.lognormal(np.log(350) - 0.28, 0.75, size=n)), 20, 2000).astype(int)
+    lens[::61] = 0
+    res, off = sd.pack_sequences([sd.random_residues(rng, int(L)) for L in lens])
+    db = swmi.Database(res, off, 20)
+    try:
+        for L, thr in [(144, 0), (400, 0), (1000, 0), (144, 40), (1000, 40)]:
+            q = sd.random_residues(rng, L)
+            db.set_opts(tier=1, sat_threshold=thr)
+            print(f"small all-long n={n} qlen={L} thr={thr}", flush=True)
+            exp = orc.search(q, res, off, M, 2, 12)
+            expect_equal(db.search(q, M, 2, 12), exp, f"n {n} qlen {L} thr {thr}")
+            st = db.stats()
+            assert st["inter_cells"] == 0 and st["intra_pairs"] == n
+            packed = not (L > 256 and L <= 512 and n < 1536)
+            assert st["fused_long"] == (0 if packed else 1), (L, n, st["fused_long"])
+            if thr:
+                assert st["recomputed_pairs"] == int((exp >= thr).sum())
+    finally:
+        db.close()
+
+
 def test_packed_in_kernel_recompute_batch_graph(swmi, orc):
     """The packed wave-per-pair kernel recomputes the halves it flags in int32
     inside its own launch, one subject per wave of the flagging workgroup, in
