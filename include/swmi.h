@@ -317,9 +317,11 @@ void sw_server_stop(sw_server *srv);
 /* ---- databases larger than device memory ----
  * Section III's workflow: the database is sorted and indexed offline, and the
  * search loads it chunk by chunk.  The index file holds the subjects sorted by
- * length and cut into chunks of about chunk_residues residues, each stored in
- * the packed device layout of sw_db_open (its subjects in ascending database
- * order).  A search keeps the whole index on the device when it fits the
+ * length and dealt round-robin over chunks of at most chunk_residues residues
+ * (so that every chunk holds the whole length distribution), or, when the
+ * longest subject exceeds a quarter of a chunk, cut into consecutive runs of
+ * the length order; each chunk is stored in the packed device layout of
+ * sw_db_open (its subjects in ascending database order).  A search keeps the whole index on the device when it fits the
  * memory budget; otherwise it streams the chunks through two device slots,
  * loading chunk c+1 (host thread, copies on the slot's own stream) while
  * chunk c is searched.  Results equal sw_db_search_batch on the same database

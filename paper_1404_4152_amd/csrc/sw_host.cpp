@@ -2564,18 +2564,39 @@ int sw_index_write(const char *path, const uint8_t *residues, const int64_t *off
     std::vector<int32_t> order(n_seqs);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return len[x] < len[y]; });
-    // chunk boundaries in length order (at least one subject per chunk)
-    std::vector<int64_t> cut{0};
-    int64_t acc = 0;
-    for (int64_t i = 0; i < n_seqs; ++i) {
-        if (acc > 0 && acc + len[order[i]] > chunk_residues) {
-            cut.push_back(i);
-            acc = 0;
+    // Chunk assignment.  Consecutive runs of the length order would leave the
+    // last chunks with only long subjects, too few to fill the chip lane-per-
+    // subject, so those chunks would run entirely on the wave-per-pair kernel.
+    // Instead, when subjects are short next to a chunk, the length order is
+    // dealt round-robin over nc chunks: every chunk then holds the whole length
+    // distribution.  Dealt this way a chunk exceeds the mean by at most two of
+    // the longest subjects, so nc = ceil(total / (chunk_residues - 2 max_len))
+    // keeps each within chunk_residues.  Otherwise (a single chunk, or
+    // subjects longer than a quarter of a chunk) the length order is cut into
+    // consecutive runs (at least one subject per chunk).
+    int64_t max_len = 0;
+    for (int64_t i = 0; i < n_seqs; ++i) max_len = std::max(max_len, len[i]);
+    const int64_t total = offsets[n_seqs];
+    const int64_t room = chunk_residues - 2 * max_len;
+    std::vector<std::vector<int32_t>> members;
+    int64_t layout = 0;
+    if (total > chunk_residues && 4 * max_len <= chunk_residues && room > 0) {
+        const int64_t nc = (total + room - 1) / room;
+        members.assign((size_t)nc, {});
+        for (int64_t r = 0; r < n_seqs; ++r) members[(size_t)(r % nc)].push_back(order[r]);
+        layout = 1;
+    } else {
+        int64_t acc = 0;
+        for (int64_t i = 0; i < n_seqs; ++i) {
+            if (members.empty() || (acc > 0 && acc + len[order[i]] > chunk_residues)) {
+                members.push_back({});
+                acc = 0;
+            }
+            members.back().push_back(order[i]);
+            acc += len[order[i]];
         }
-        acc += len[order[i]];
     }
-    if (n_seqs > 0) cut.push_back(n_seqs);
-    const int64_t n_chunks = (int64_t)cut.size() - 1;
+    const int64_t n_chunks = (int64_t)members.size();
 
     FILE *f = fopen(path, "wb");
     if (!f) return fail(SW_EINVAL, "index: cannot create %s", path);
@@ -2588,11 +2609,12 @@ int sw_index_write(const char *path, const uint8_t *residues, const int64_t *off
     hdr.total_res = offsets[n_seqs];
     hdr.n_chunks = n_chunks;
     hdr.chunk_residues = chunk_residues;
+    hdr.reserved[0] = layout;   // 0: consecutive runs of the length order, 1: dealt round-robin
     std::vector<ChunkEntry> table((size_t)n_chunks);
     int64_t pos = al64((int64_t)sizeof hdr + n_chunks * (int64_t)sizeof(ChunkEntry));
     for (int64_t c = 0; c < n_chunks; ++c) {
         // the chunk's subjects in ascending database order
-        std::vector<int32_t> ids(order.begin() + cut[c], order.begin() + cut[c + 1]);
+        std::vector<int32_t> ids = std::move(members[(size_t)c]);
         std::sort(ids.begin(), ids.end());
         const int64_t n = (int64_t)ids.size();
         std::vector<int64_t> loff(n + 1, 0);

@@ -3,12 +3,13 @@ chunk (section III's offline index and chunked loading), against the same
 database opened whole and against the oracle.
 
 The database has 1,200,000 subjects (mean 30 residues) plus 40 subjects
-longer than the lane-per-subject groups take, cut into 7 chunks of up to 6 M
-residues: the three with the shortest subjects hold enough of them for
-lane-per-subject groups, the others run wave-per-pair, the last holds the
-long ones.  A memory budget of 40 MiB (the index needs about 63 MiB on the
-device) forces streaming through two device slots; the default budget keeps
-every chunk resident.
+longer than the lane-per-subject groups take, dealt round-robin in length
+order into 7 chunks of up to 6 M residues: each holds about 171,000 subjects
+of every length, enough for lane-per-subject groups, and a few long ones.  A
+memory budget of 40 MiB forces streaming through two device slots; the
+default budget keeps every chunk resident.  A second index, whose subjects
+are long next to its chunks, is cut into consecutive runs of the length
+order instead: every chunk runs wave-per-pair.
 """
 import numpy as np
 import pytest
@@ -118,3 +119,34 @@ def test_index_budget_too_small(data):
     with pytest.raises(swmi.SwError) as e:
         swmi.Index(path, memory_budget=10 << 20)
     assert e.value.code == swmi.SW_ENOMEM and "budget" in str(e.value)
+
+
+def test_index_length_runs_streamed(tmp_path):
+    """Subjects of up to 4,530 residues in chunks of 15,000: too long to deal
+    round-robin (more than a quarter of a chunk), so the chunks are
+    consecutive runs of the length order (the file says which), each too small
+    for lane-per-subject groups; streamed under a small budget, the results
+    equal the whole database's."""
+    import paper_1404_4152_amd as swmi
+    rng = np.random.Generator(np.random.PCG64(77))
+    res, off = sd.make_db(3000, 300, 0, 9000, seed=77)
+    path = tmp_path / "runs.swx"
+    swmi.sw_index_write(str(path), res, off, 20, 15_000)
+    assert int(np.frombuffer(path.read_bytes()[:72], np.int64, 1, 48)[0]) == 0   # header: layout 0
+    M = sd.blosum_style_matrix()
+    queries = [sd.random_residues(rng, n) for n in (50, 300, 1100)]
+    db = swmi.Database(res, off, 20)
+    try:
+        wts, wti, wal = db.search_batch(queries, M, 2, 12, 20, all_scores=True)
+    finally:
+        db.close()
+    print("length-run index, streamed", flush=True)
+    ix = swmi.Index(str(path), memory_budget=256 << 10)
+    try:
+        ts, ti, al = ix.search_batch(queries, M, 2, 12, 20, all_scores=True)
+        st = ix.stats()
+    finally:
+        ix.close()
+    assert st["resident"] == 0 and st["chunks"] > 20
+    assert np.array_equal(al, wal)
+    assert np.array_equal(ts, wts) and np.array_equal(ti, wti)

@@ -50,7 +50,8 @@ def swmi():
     return p
 
 
-@pytest.mark.parametrize("n,chunk", [(3000, 40_000), (200_000, 30_000_000), (1, 10), (50, 1)])
+@pytest.mark.parametrize("n,chunk", [(3000, 40_000), (200_000, 30_000_000), (200_000, 12_000_000),
+                                     (1, 10), (50, 1)])
 def test_index_file_layout(swmi, tmp_path, n, chunk):
     res, off = sd.make_db(n, 300, 0, 9000, seed=n)   # zero-length subjects included
     lens = np.diff(off)
@@ -61,9 +62,17 @@ def test_index_file_layout(swmi, tmp_path, n, chunk):
     assert h["magic"] == b"SWMIIDX1" and h["version"] == 1 and h["alphabet"] == 20
     assert h["n_seqs"] == n and h["total_res"] == off[-1] and h["chunk_residues"] == chunk
     nchunks = int(h["n_chunks"])
+    layout = int(h["reserved"][0])
     table = np.frombuffer(buf, ENTRY, nchunks, HDR.itemsize)
     seen = []
     prev_max = -1
+    # the length order (stable), dealt round-robin over the chunks (layout 1)
+    # or cut into consecutive runs (layout 0)
+    rank_order = np.argsort(lens, kind="stable")
+    if layout == 1:
+        assert off[-1] > chunk and 4 * lens.max() <= chunk and nchunks >= 2
+    else:
+        assert layout == 0
     R = 21
     for e in table:
         c = read_chunk(buf, int(e["file_off"]))
@@ -73,8 +82,11 @@ def test_index_file_layout(swmi, tmp_path, n, chunk):
         clen = lens[ids]
         assert np.array_equal(np.diff(c["offsets"]), clen)
         assert clen.sum() <= chunk or len(ids) == 1
-        assert clen.min() >= prev_max                           # length order across chunks
-        prev_max = clen.max()
+        if layout == 1:
+            assert np.array_equal(ids, np.sort(rank_order[len(seen)::nchunks]))
+        else:
+            assert clen.min() >= prev_max                       # length order across chunks
+            prev_max = clen.max()
         for i in np.random.default_rng(0).choice(len(ids), size=min(50, len(ids)), replace=False):
             a, b = c["offsets"][i], c["offsets"][i + 1]
             assert np.array_equal(c["residues"][a:b], res[off[ids[i]]:off[ids[i] + 1]])
