@@ -160,6 +160,16 @@ int intra_T_for(int64_t max_qlen) {
     return 16;
 }
 
+// Query columns a wave-per-pair pass evaluates for a query: whole passes of
+// 64 x ti columns, except that the packed kernel at 16 columns per lane runs
+// its last pass at 4, 8 or 12 when those hold the rest.
+int64_t long_columns(int64_t qlen, int ti, bool packed) {
+    const int64_t pw = 64LL * ti;
+    if (!packed || ti != 16) return round_up(qlen, pw);
+    const int64_t full = (qlen - 1) / pw, rem = qlen - full * pw;
+    return full * pw + (rem <= 256 ? 256 : rem <= 512 ? 512 : rem <= 768 ? 768 : 1024);
+}
+
 int qlen_bucket(int64_t qlen) {
     int b = 0;
     while ((64LL << b) < qlen && b < 20) ++b;
@@ -942,7 +952,7 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     for (int64_t g = 0; g < g_cut; ++g) inter_rows += (int64_t)db->grp_rows[g] * kGroup;
     for (int32_t q = 0; q < nq; ++q)
         padded += round_up((int64_t)mpad[q], (int64_t)plan.strip) * inter_rows +
-                  round_up(qlen[q], 64LL * L.Ti) * long_res;
+                  long_columns(qlen[q], L.Ti, L.packed_long) * long_res;
     s.padded_cells = padded;
     s.inter_cells = sum_qlen * db->grp_res_prefix[g_cut];
     s.recomputed_pairs = ctr_h[1];
