@@ -194,9 +194,15 @@ def run_plain(args, swmi, sd, torch):
     torch.cuda.synchronize()
     all_sts = []
     t = time.perf_counter()
+    t_log = t
     for i in range(args.steps):
         all_sts += step()
-        log(f"[bench] step {i + 1}/{args.steps} done ({time.perf_counter() - t:.1f}s)")
+        # a progress line at most once a second (and after the last step):
+        # a short step would otherwise time the logging too
+        now = time.perf_counter()
+        if now - t_log >= 1.0 or i + 1 == args.steps:
+            log(f"[bench] step {i + 1}/{args.steps} done ({now - t:.1f}s)")
+            t_log = now
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     align = None if args.no_align else run_align(args, swmi, db, w, res, off, queries, M)

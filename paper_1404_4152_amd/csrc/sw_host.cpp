@@ -149,7 +149,8 @@ struct Plan {
     int profile = SW_PROFILE_PAIR;
 };
 
-constexpr int kIntraWaves = 4;   // waves per workgroup of the wave-per-pair kernel (long list)
+constexpr int kIntraWaves = 4;
+constexpr size_t kResHead = 64;   // bytes of pass counters ahead of the top-k results   // waves per workgroup of the wave-per-pair kernel (long list)
 // Subjects longer than this never go into a lane-per-subject group: one lane
 // would hold its SIMD too long and its boundary buffer would be large.
 constexpr int64_t kGroupMaxLen = 8192;
@@ -274,8 +275,11 @@ struct sw_db {
     DevBuf d_res, d_off, d_codes, d_grp_base, d_grp_rows, d_grp_ids;
     DevBuf d_long_ids;                // long_ids on the device (sw_db_search_dev_noalloc)
     // per-call workspaces (plain and batched searches)
-    DevBuf w_stage, w_scores, w_counters, w_ovf, w_scr_inter, w_scr_intra, w_topk, w_top;
-    HostBuf h_stage;
+    DevBuf w_stage, w_scores, w_ovf, w_scr_inter, w_scr_intra, w_topk;
+    // the pass counters (64 bytes), then the top-k indices and scores, so that
+    // one copy brings all of them back into the pinned h_res
+    DevBuf w_res;
+    HostBuf h_stage, h_res;
     DevBuf w_al_meta, w_al_dir, w_al_ops, w_al_scr;   // sw_db_align workspaces
     HostBuf h_al;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -794,7 +798,6 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     const StageLayout sl = stage_layout(nq, prof_bytes, it, code_bytes);
     TRY(db->w_stage.reserve(sl.total));
     TRY(db->w_scores.reserve((size_t)nq * n * 4 + 4));
-    TRY(db->w_counters.reserve(256));
     TRY(db->w_ovf.reserve((size_t)nq * n * 8 + 8));
     if (n_inter > 0)
         TRY(db->w_scr_inter.reserve((size_t)L.grid_inter * plan.waves * rows_alloc * 512));
@@ -803,10 +806,10 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
                                             : (int64_t)L.grid_long * kIntraWaves;
     const int64_t intra_slots = std::max<int64_t>(long_slots, L.grid_ovf);
     TRY(db->w_scr_intra.reserve((size_t)intra_slots * intra_scratch_rows(db) * 8));
-    if (k > 0) {
-        TRY(db->w_topk.reserve(topk_work_bytes(nq, k)));
-        TRY(db->w_top.reserve((size_t)nq * k * 12));
-    }
+    if (k > 0) TRY(db->w_topk.reserve(topk_work_bytes(nq, k)));
+    const size_t res_bytes = kResHead + (size_t)nq * k * 12;
+    TRY(db->w_res.reserve(res_bytes));
+    TRY(db->h_res.reserve(res_bytes));
 
     // ---- host staging (the previous call may still be reading it) ----
     TRY(db->h_stage.reserve(sl.total));
@@ -861,11 +864,11 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     pb.ovf_q = db->w_ovf.as<int32_t>();
     pb.ovf_id = pb.ovf_q + (size_t)nq * n;
     pb.ovf_cap = (int64_t)nq * n;
-    pb.counters = db->w_counters.as<int32_t>();
+    pb.counters = db->w_res.as<int32_t>();
     pb.scr_inter = db->w_scr_inter.as<uint32_t>();
     pb.scr_rows = rows_alloc;
     pb.scr_intra = db->w_scr_intra.as<int32_t>();
-    int64_t *d_ti = k > 0 ? db->w_top.as<int64_t>() : nullptr;
+    int64_t *d_ti = k > 0 ? (int64_t *)(db->w_res.as<uint8_t>() + kResHead) : nullptr;
     int32_t *d_ts = d_ti ? (int32_t *)(d_ti + (size_t)nq * k) : nullptr;
 
     auto enqueue_all = [&](hipStream_t s, bool events) -> int {
@@ -924,15 +927,18 @@ int run_search(sw_db *db, int32_t nq, const uint8_t *q_res, const int64_t *q_off
     } else {
         TRY(enqueue_all(st, true));
     }
-    if (k > 0) {
-        HIPX(hipMemcpyAsync(top_s, d_ts, (size_t)nq * k * 4, hipMemcpyDeviceToHost, st));
-        HIPX(hipMemcpyAsync(top_i, d_ti, (size_t)nq * k * 8, hipMemcpyDeviceToHost, st));
-    }
     if (scores_host && n > 0)
         HIPX(hipMemcpyAsync(scores_host, pb.scores, (size_t)nq * n * 4, hipMemcpyDeviceToHost, st));
-    int32_t ctr_h[4] = {0, 0, 0, 0};
-    HIPX(hipMemcpyAsync(ctr_h, pb.counters, 16, hipMemcpyDeviceToHost, st));
+    // counters and top-k in one copy to pinned memory
+    HIPX(hipMemcpyAsync(db->h_res.p, db->w_res.p, res_bytes, hipMemcpyDeviceToHost, st));
     HIPX(hipStreamSynchronize(st));
+    int32_t ctr_h[4];
+    std::memcpy(ctr_h, db->h_res.p, sizeof ctr_h);
+    if (k > 0) {
+        const uint8_t *hr = db->h_res.as<uint8_t>() + kResHead;
+        std::memcpy(top_i, hr, (size_t)nq * k * 8);
+        std::memcpy(top_s, hr + (size_t)nq * k * 8, (size_t)nq * k * 4);
+    }
 
     float ms_k = 0, ms_i = -1, ms_r = -1, ms_l = -1;
     HIPX(hipEventElapsedTime(&ms_k, db->ev[0], db->ev[2]));
