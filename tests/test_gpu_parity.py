@@ -465,6 +465,36 @@ def test_topk_with_heavy_ties(swmi, orc, k):
             db.close()
 
 
+@pytest.mark.parametrize("n", [1, 65, 4096, 4097])
+def test_topk_small_rows(swmi, orc, n):
+    """Rows of at most 4,096 subjects take the one-workgroup sort, larger rows
+    the radix select: both sides of that boundary, a one-subject database and
+    a k past n.  Heavy ties (a three-letter alphabet, short subjects), single
+    queries and a batch."""
+    rng = np.random.Generator(np.random.PCG64(4000 + n))
+    A = 3
+    M = np.array([[2, -1, -1], [-1, 2, -1], [-1, -1, 2]], np.int8)
+    res, off = random_db(rng, n, A, 0, 12)
+    qs = [sd.uniform_residues(rng, L, A) for L in (4, 9)]
+    db = swmi.Database(res, off, A)
+    try:
+        exps = [orc.search(q, res, off, M, 1, 2) for q in qs]
+        for k in (1, 10, 16, 17, 70):
+            print(f"topk small rows n={n} k={k}", flush=True)
+            for q, exp in zip(qs, exps):
+                ts, ti = db.topk(q, M, 1, 2, k)
+                es, ei = oracle.topk(exp, k)
+                expect_equal(ts, es, f"n {n} k {k} scores")
+                expect_equal(ti, ei, f"n {n} k {k} indices")
+            ts, ti = db.search_batch(qs, M, 1, 2, k)
+            for x, exp in enumerate(exps):
+                es, ei = oracle.topk(exp, k)
+                expect_equal(ts[x], es, f"batch n {n} k {k} scores")
+                expect_equal(ti[x], ei, f"batch n {n} k {k} indices")
+    finally:
+        db.close()
+
+
 def test_batch_matches_single_queries(swmi, orc):
     rng = np.random.Generator(np.random.PCG64(77))
     M = sd.blosum_style_matrix()
