@@ -194,12 +194,16 @@ def run_plain(args, swmi, sd, torch):
     torch.cuda.synchronize()
     all_sts = []
     t = time.perf_counter()
-    t_log = t
+    t_log = t_prev = t
+    step_ms = []
     for i in range(args.steps):
         all_sts += step()
+        # every call returns synchronised, so the step's own wall time is known
+        now = time.perf_counter()
+        step_ms.append((now - t_prev) * 1e3)
+        t_prev = now
         # a progress line at most once a second (and after the last step):
         # a short step would otherwise time the logging too
-        now = time.perf_counter()
         if now - t_log >= 1.0 or i + 1 == args.steps:
             log(f"[bench] step {i + 1}/{args.steps} done ({now - t:.1f}s)")
             t_log = now
@@ -217,6 +221,7 @@ def run_plain(args, swmi, sd, torch):
         "metric": "GCUPS + % integer-VALU peak (batched/served vs plain); p50/p99 query latency",
         "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 2),
+        "ms_per_step_median": round(float(np.median(step_ms)), 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16x2+i32",
         "data": "synthetic",
         "config": {"workload": w.name, "subjects": len(off) - 1, "residues": int(len(res)),
@@ -241,6 +246,13 @@ def run_plain(args, swmi, sd, torch):
         # subject, queries to the strip or to the wave-per-pair pass width
         "padding": round(sum(s["padded_cells"] for s in all_sts) /
                          max(sum(s["cells"] for s in all_sts), 1) - 1, 4),
+        # [query length, GCUPS over the device time of its search's kernels],
+        # each query's calls of the timed steps averaged (the paper's
+        # GCUPS-against-query-length curve)
+        "per_query": [[len(q), round(len(q) * int(len(res)) * args.steps /
+                                     (sum(all_sts[i * len(queries) + x]["kernel_ms"]
+                                          for i in range(args.steps)) / 1e3) / 1e9, 1)]
+                      for x, q in enumerate(queries)],
     }
     if align:
         out["align_topk"] = align
@@ -607,8 +619,8 @@ def run_served(args, swmi, sd, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="plain_scale",
                     choices=["plain_scale", "plain_small", "long_tail"])
     ap.add_argument("--k", type=int, default=10)
