@@ -150,3 +150,43 @@ def test_index_length_runs_streamed(tmp_path):
     assert st["resident"] == 0 and st["chunks"] > 20
     assert np.array_equal(al, wal)
     assert np.array_equal(ts, wts) and np.array_equal(ti, wti)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_index_random_configs(tmp_path, seed):
+    """Seeded draws of database size, lengths, chunk size (dealt or in runs)
+    and memory budget (resident or streamed): the index's scores and top-k
+    equal the whole database's."""
+    import paper_1404_4152_amd as swmi
+    rng = np.random.Generator(np.random.PCG64(31_000 + seed))
+    n = int(rng.choice([50, 2000, 20000]))
+    hi = int(rng.choice([40, 400, 3000]))
+    lens = rng.integers(0, hi + 1, size=n)
+    res, off = sd.pack_sequences([sd.random_residues(rng, int(L)) for L in lens])
+    total = int(off[-1])
+    chunk = int(max(1, total // int(rng.choice([1, 3, 7, 40]))))
+    path = tmp_path / "r.swx"
+    swmi.sw_index_write(str(path), res, off, 20, chunk)
+    layout = int(np.frombuffer(path.read_bytes()[:72], np.int64, 1, 48)[0])
+    M = sd.blosum_style_matrix()
+    qs = [sd.random_residues(rng, int(L)) for L in rng.integers(1, 900, size=2)]
+    k = int(rng.choice([1, 10, 64]))
+    budget = int(rng.choice([0, 1 << 20, 8 << 20]))
+    print(f"index seed {seed}: n {n} hi {hi} chunk {chunk} layout {layout} budget {budget} k {k}", flush=True)
+    db = swmi.Database(res, off, 20)
+    try:
+        wts, wti, wal = db.search_batch(qs, M, 2, 12, k, all_scores=True)
+    finally:
+        db.close()
+    try:
+        ix = swmi.Index(str(path), memory_budget=budget)
+    except swmi.SwError as e:
+        # a budget below two of the largest chunk is refused, and says so
+        assert e.code == swmi.SW_ENOMEM and "budget" in str(e) and budget > 0
+        return
+    try:
+        ts, ti, al = ix.search_batch(qs, M, 2, 12, k, all_scores=True)
+    finally:
+        ix.close()
+    assert np.array_equal(al, wal)
+    assert np.array_equal(ts, wts) and np.array_equal(ti, wti)
