@@ -1205,14 +1205,17 @@ int intra_lds_bytes(int R, int T) { return R * (64 * T + 8) * 2; }
 // t - l, so no register shifts feeder values along the wave each step.  The
 // last lane's outputs go through the same ring, read back once per 64 rows.
 // ---------------------------------------------------------------------------
-// Steps of the packed kernel run in groups of kGrp2; row X of a group takes,
-// in column class c, the floor FW[X + c].
-constexpr int kGrp2 = 4;
-
-template <int T, int X>
+// Steps of the packed kernel run in groups of G2 steps; row X of a group
+// takes, in column class c, the floor FW[X + c].  The loads of a group's steps
+// are issued together, so a group pays the two dependent LDS round trips
+// (ring, then profile rows) once.  The kernel at 4 columns per lane, whose
+// steps are short and which often runs one wave per SIMD (small databases),
+// takes groups of 8, halving that exposed latency per step; elsewhere groups
+// of 4 keep the registers within the occupancy the kernel is built for.
+template <int T, int X, int G2>
 __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *pa,
                                            const uint2 *pb, const LaneFrame &ops, h2 hdiag, h2 f,
-                                           const h2 (&FW)[kFrameCols + kGrp2 - 1], h2 (&B)[2],
+                                           const h2 (&FW)[kFrameCols + G2 - 1], h2 (&B)[2],
                                            h2 &hout, h2 &fout) {
     static_assert(kFrameCols == 4 && T % kFrameCols == 0, "a lane holds whole column groups");
     // (low half from subject a's row, high half from subject b's row)
@@ -1247,7 +1250,7 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
 }
 
 
-template <int T, bool HAS_IN, bool HAS_OUT>
+template <int T, bool HAS_IN, bool HAS_OUT, int G2 = 4>
 __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame &ops,
                                             const uint16_t *prof, int RS, int32_t *wsc,
                                             uint32_t *ring, const uint8_t *sa, const uint8_t *sb,
@@ -1258,6 +1261,7 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
     // with outputs, the last block's collection needs step 64 * nblk + 63;
     // steps run in whole groups (past the last row every lane reads pad
     // rows, whose zero scores raise no best)
+    constexpr int kGrp2 = G2;
     const int steps = HAS_OUT ? nblk * 64 + 64 : (n + 63 + kGrp2 - 1) / kGrp2 * kGrp2;
     const h2 pa2 = ops.palpha, pag = ops.k(kGrp2);
     const float alpha = (float)ops.alpha;
@@ -1349,10 +1353,14 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
                 const uint2 *pa = (const uint2 *)(prof + (__umul24(e[kRingA], RS) + lane * T));
                 const uint2 *pb = (const uint2 *)(prof + (__umul24(e[kRingB], RS) + lane * T));
                 switch (x) {
-                case 0: intra2_row<T, 0>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
-                case 1: intra2_row<T, 1 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
-                case 2: intra2_row<T, 2 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
-                default: intra2_row<T, 3 % kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 0: intra2_row<T, 0, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 1: intra2_row<T, 1 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 2: intra2_row<T, 2 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 3: intra2_row<T, 3 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 4: intra2_row<T, 4 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 5: intra2_row<T, 5 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                case 6: intra2_row<T, 6 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
+                default: intra2_row<T, 7 % kGrp2, kGrp2>(H, E, pa, pb, ops, hb_prev, fin, FW, B, hout, fout); break;
                 }
                 hb_prev = hin;
                 B[0] += pa2;
@@ -1410,10 +1418,11 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
 // At T = 16 the protein-sized profile already holds a CU to three of these
 // workgroups, so the kernel may use the registers of three waves per SIMD.
 template <int T, int W>
-__global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraArgs a) {
+__global__ void __launch_bounds__(W * 64, T == 8 ? 4 : 3) intra2_kernel(IntraArgs a) {
     typedef Lane<TIER_F16X2> L;
     constexpr int PW = 64 * T;          // query columns per pass
     constexpr int RS = PW + 8;          // fp16 entries per profile row (padded)
+    constexpr int kG2 = T == 4 ? 8 : 4; // steps per group of the T-wide passes
     extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     uint16_t *prof = (uint16_t *)lds;
     __shared__ int s_item, s_nflag;
@@ -1486,11 +1495,11 @@ __global__ void __launch_bounds__(W * 64, T == 16 ? 3 : 4) intra2_kernel(IntraAr
                 }
             }
             if (has_in) {
-                if (has_out) intra2_pass<T, true, true>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
-                else intra2_pass<T, true, false>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                if (has_out) intra2_pass<T, true, true, kG2>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, true, false, kG2>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
             } else {
-                if (has_out) intra2_pass<T, false, true>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
-                else intra2_pass<T, false, false>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                if (has_out) intra2_pass<T, false, true, kG2>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
+                else intra2_pass<T, false, false, kG2>(a, ops, prof, RS, wsc, ring, sa, sb, na, nb, pad, best);
             }
         }
 #pragma unroll
