@@ -1416,7 +1416,8 @@ __device__ __forceinline__ void intra2_pass(const IntraArgs &a, const LaneFrame 
 }
 
 // At T = 16 the protein-sized profile already holds a CU to three of these
-// workgroups, so the kernel may use the registers of three waves per SIMD.
+// workgroups, so the kernel may use the registers of three waves per SIMD; at
+// T = 4 its groups of 8 steps need them (see intra2_row).
 template <int T, int W>
 __global__ void __launch_bounds__(W * 64, T == 8 ? 4 : 3) intra2_kernel(IntraArgs a) {
     typedef Lane<TIER_F16X2> L;
