@@ -2212,12 +2212,19 @@ int align_pairs(sw_db *db, const uint8_t *query, int64_t qlen, const sw_scoring 
         }
         const int32_t nb = b1 - b0;
         const size_t meta_bytes = (size_t)nb * (3 * 8 + 3 * 4 + 6 * 4) + (size_t)R * mpad + 256;
-        TRY(db->w_al_meta.reserve(meta_bytes));
-        TRY(db->h_al.reserve(meta_bytes));
-        TRY(db->w_al_dir.reserve(std::max<size_t>(dir_bytes, 16)));
-        TRY(db->w_al_ops.reserve(std::max<size_t>(ops_n * 4, 4)));
+        // Buffers grow by half again at least (the direction bytes up to a
+        // batch's bound): calls whose sizes creep up, as for queries of
+        // growing length, would otherwise free and allocate on every call.
+        auto grown = [](size_t want, const DevBuf &b, size_t cap) {
+            return want <= b.bytes ? want : std::max(want, std::min(cap, b.bytes + b.bytes / 2));
+        };
+        TRY(db->w_al_meta.reserve(grown(meta_bytes, db->w_al_meta, SIZE_MAX)));
+        TRY(db->h_al.reserve(std::max(meta_bytes, db->w_al_meta.bytes)));
+        TRY(db->w_al_dir.reserve(grown(std::max<size_t>(dir_bytes, 16), db->w_al_dir, kAlignBatchBytes)));
+        TRY(db->w_al_ops.reserve(grown(std::max<size_t>(ops_n * 4, 4), db->w_al_ops, SIZE_MAX)));
         const int grid = (nb + kAlignWaves - 1) / kAlignWaves;
-        TRY(db->w_al_scr.reserve((size_t)grid * kAlignWaves * (size_t)max_len_pad * 8));
+        TRY(db->w_al_scr.reserve(grown((size_t)grid * kAlignWaves * (size_t)max_len_pad * 8, db->w_al_scr,
+                                       SIZE_MAX)));
         // host staging: ids, dir offsets, ops offsets (int64), then the profile
         HIPX(hipStreamSynchronize(st));
         uint8_t *h = db->h_al.as<uint8_t>();
