@@ -1413,7 +1413,11 @@ int server_pass(sw_server *s, const std::vector<std::shared_ptr<Request>> &fresh
             const int64_t L = (int64_t)r->query.size();
             const int32_t m = (int32_t)round_up(L, kQPad);
             DevBuf &pb = *s->prof[r->slot];
-            TRY(pb.reserve((size_t)R * m));
+            // grow-only, by doubling from 2,048 columns: a slot meets longer
+            // queries over time, and each reallocation frees device memory
+            // (which waits for the device) between passes
+            const size_t want = (size_t)R * m;
+            if (want > pb.bytes) TRY(pb.reserve(std::max({want, 2 * pb.bytes, (size_t)R * 2048})));
             staging.resize((size_t)R * m);
             sw_scoring sc{db->alphabet, r->matrix.data(), r->alpha, r->beta};
             write_profile((int8_t *)staging.data(), r->query.data(), L, m, &sc, R);
