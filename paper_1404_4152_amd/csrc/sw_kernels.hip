@@ -349,25 +349,43 @@ struct FrameStrip {
                                                const uint4 *nxt, uint32_t hb_prev, uint32_t fin,
                                                const V *FL, V (&B)[2], uint32_t &hout,
                                                uint32_t &fout) {
-        V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
 #pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) Pn[j4] = nxt[j4];
+        // The cells of FrameStrip::cell, in an order that puts independent
+        // work between each column's dependent steps h -> t -> f: gfx950 holds
+        // a packed instruction back one cycle when it reads the result of the
+        // packed instruction just before it.  Between h and t goes the next
+        // column's diagonal sum (H[j] still holds row r - 1 there); between t
+        // and f the running best of an even column, and the E update of the
+        // column before (E[j] is next read by the row below).
+        V d = as_v<V>(hb_prev) + as_v<V>(Pc[0].x);
+        V tp = d;
 #pragma unroll
-        for (int j4 = 0; j4 < T / 4; ++j4) {
-            const int j = j4 * 4;
-            const V h0 = cell<0>(ops, H[j], E[j], Pc[j4].x, hdiag, f, FL[0]);
-            cell<1>(ops, H[j + 1], E[j + 1], Pc[j4].y, hdiag, f, FL[1]);
-            B[0] = max3(B[0], h0, hdiag);          // hdiag = H(r-1, j+1)
-            const V h2v = cell<2>(ops, H[j + 2], E[j + 2], Pc[j4].z, hdiag, f, FL[2]);
-            cell<3>(ops, H[j + 3], E[j + 3], Pc[j4].w, hdiag, f, FL[3]);
-            B[1] = max3(B[1], h2v, hdiag);         // hdiag = H(r-1, j+3)
+        for (int j = 0; j < T; ++j) {
+            const V h = max3(d, E[j], f);
+            if (j + 1 < T) d = H[j] + as_v<V>(pval(Pc, j + 1));
+            const V t = h + ops.nu;
+            // classes 0 and 2: (r, j) and (r - 1, j + 1) share an offset
+            if (!(j & 1)) B[(j >> 1) & 1] = max3(B[(j >> 1) & 1], h, H[j + 1]);
+            if (j > 0) E[j - 1] = max3(E[j - 1], tp, FL[(j - 1) & 3]);
+            f = __builtin_elementwise_maximum(f, t);
+            if ((j & 3) == 3) f += ops.ngroup;
+            H[j] = h;
+            tp = t;
         }
+        E[T - 1] = max3(E[T - 1], tp, FL[(T - 1) & 3]);
         hout = as_u(H[T - 1]);
         fout = as_u(f);
 #pragma unroll
         for (int j = 0; j < T; ++j) asm volatile("" : "+v"(H[j]), "+v"(E[j]));
         asm volatile("" : "+v"(B[0]), "+v"(B[1]));
+    }
+
+    // Column j's value of a row of profile quads.
+    static __device__ __forceinline__ uint32_t pval(const uint4 (&P)[T / 4], int j) {
+        const uint4 &q = P[j >> 2];
+        return (j & 3) == 0 ? q.x : (j & 3) == 1 ? q.y : (j & 3) == 2 ? q.z : q.w;
     }
 
     // All rows of one group against one strip; `best_io` is a true value on
@@ -1229,22 +1247,26 @@ __device__ __forceinline__ void intra2_row(h2 (&H)[T], h2 (&E)[T], const uint2 *
         sv[4 * j4 + 3] = __builtin_amdgcn_perm(Bv.y, A.y, 0x07060302u);
     }
     // The diagonal operand of column j+1 is taken from H[j] before H[j] is
-    // overwritten, so each new H goes into the register of the old one.
+    // overwritten, so each new H goes into the register of the old one.  The
+    // steps are ordered as in FrameStrip::row, with independent work between
+    // each column's dependent packed steps h -> t -> f.
     h2 d = hdiag + as_v<h2>(sv[0]);
+    h2 tp = d;
 #pragma unroll
     for (int j = 0; j < T; ++j) {
-        const h2 dn = j + 1 < T ? H[j] + as_v<h2>(sv[j + 1]) : d;
         const h2 h = FrameStrip<4>::max3(d, E[j], f);
+        if (j + 1 < T) d = H[j] + as_v<h2>(sv[j + 1]);
         const h2 t = h + ops.nu;
-        E[j] = FrameStrip<4>::max3(E[j], t, FW[X + (j & 3)]);
-        f = __builtin_elementwise_maximum(f, t);
-        if ((j & 3) == 3) f += ops.ngroup;
-        H[j] = h;
         // (r, j) and (r - 1, j + 1) share an offset for even j; H[j + 1]
         // still holds row r - 1
         if (!(j & 1)) B[(j & 2) >> 1] = FrameStrip<4>::max3(B[(j & 2) >> 1], h, H[j + 1]);
-        d = dn;
+        if (j > 0) E[j - 1] = FrameStrip<4>::max3(E[j - 1], tp, FW[X + ((j - 1) & 3)]);
+        f = __builtin_elementwise_maximum(f, t);
+        if ((j & 3) == 3) f += ops.ngroup;
+        H[j] = h;
+        tp = t;
     }
+    E[T - 1] = FrameStrip<4>::max3(E[T - 1], tp, FW[X + ((T - 1) & 3)]);
     hout = H[T - 1];
     fout = f;
 }
