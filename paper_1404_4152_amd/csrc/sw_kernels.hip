@@ -757,20 +757,24 @@ struct FrameStripSP {
                                                uint32_t hb_prev, uint32_t fin, const V *FL,
                                                V (&B)[2], uint32_t &hout, uint32_t &fout) {
         put(spw, tn);
-        V hdiag = as_v<V>(hb_prev);
         V f = as_v<V>(fin);
+        // The steps in FrameStrip::row's order; a class-0 column's diagonal
+        // operand also takes -G alpha before its table value is added.
+        V d = (as_v<V>(hb_prev) + ops.ngroup) + as_v<V>(P[0]);
+        V tp = d;
 #pragma unroll
-        for (int j4 = 0; j4 < T / 4; ++j4) {
-            const int j = j4 * 4;
-            V hd0 = hdiag + ops.ngroup;
-            const V h0 = F::template cell<0>(ops, H[j], E[j], P[j], hd0, f, FL[0]);
-            hdiag = hd0;   // cell<0> leaves H(r-1, j) here
-            F::template cell<1>(ops, H[j + 1], E[j + 1], P[j + 1], hdiag, f, FL[1]);
-            B[0] = F::max3(B[0], h0, hdiag);
-            const V h2v = F::template cell<2>(ops, H[j + 2], E[j + 2], P[j + 2], hdiag, f, FL[2]);
-            F::template cell<3>(ops, H[j + 3], E[j + 3], P[j + 3], hdiag, f, FL[3]);
-            B[1] = F::max3(B[1], h2v, hdiag);
+        for (int j = 0; j < T; ++j) {
+            const V h = F::max3(d, E[j], f);
+            if (j + 1 < T) d = (((j + 1) & 3) == 0 ? H[j] + ops.ngroup : H[j]) + as_v<V>(P[j + 1]);
+            const V t = h + ops.nu;
+            if (!(j & 1)) B[(j >> 1) & 1] = F::max3(B[(j >> 1) & 1], h, H[j + 1]);
+            if (j > 0) E[j - 1] = F::max3(E[j - 1], tp, FL[(j - 1) & 3]);
+            f = __builtin_elementwise_maximum(f, t);
+            if ((j & 3) == 3) f += ops.ngroup;
+            H[j] = h;
+            tp = t;
         }
+        E[T - 1] = F::max3(E[T - 1], tp, FL[(T - 1) & 3]);
         hout = as_u(H[T - 1]);
         fout = as_u(f);
 #pragma unroll
