@@ -29,6 +29,7 @@ Prints one JSON line.  GCUPS = sum|Q| * sum|S| / seconds.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -434,23 +435,39 @@ def run_high_alpha(args, swmi, db, w, res, queries, M, sptr, torch):
 def run_align(args, swmi, db, w, res, off, queries, M):
     """Alignment with traceback (sw_db_align) of every query's top-k hits:
     the hits come from untimed searches; the timed region is the align calls
-    for all queries (forward and traceback kernels, their copies)."""
+    for all queries (forward and traceback kernels, their copies).  The
+    database handle's align workspaces grow to the largest call they have
+    seen, so the first pass over the queries also pays for that growth; it is
+    reported apart, and the figure is the second pass.  Python's cyclic
+    garbage collector is off while the passes run (as timeit does): the
+    binding builds a tuple per alignment run, and a full collection in a
+    process holding torch takes tens of milliseconds, which would otherwise
+    land in whichever pass it falls."""
     lens = np.diff(off)
     hits = []
     for q in queries:
         _, ti = db.topk(q, M, w.alpha, w.beta, args.k)
         hits.append(ti[ti >= 0])
-    db.align(queries[0], M, w.alpha, w.beta, hits[0])          # warm-up
     cells = sum(int(lens[h].sum()) * len(q) for q, h in zip(queries, hits))
     pairs = sum(len(h) for h in hits)
-    t = time.perf_counter()
-    for q, h in zip(queries, hits):
-        db.align(q, M, w.alpha, w.beta, h)
-    dt = time.perf_counter() - t
-    log(f"[bench] aligned the top-{args.k} of {len(queries)} queries in {dt * 1e3:.1f} ms")
+    dts = []
+    gc.collect()
+    gc.disable()
+    try:
+        for _ in range(2):
+            t = time.perf_counter()
+            for q, h in zip(queries, hits):
+                db.align(q, M, w.alpha, w.beta, h)
+            dts.append(time.perf_counter() - t)
+    finally:
+        gc.enable()
+    dt = dts[1]
+    log(f"[bench] aligned the top-{args.k} of {len(queries)} queries in {dt * 1e3:.1f} ms "
+        f"({dts[0] * 1e3:.1f} ms on the first pass)")
     return {"pairs": pairs, "cells": cells, "ms_per_query": round(dt / len(queries) * 1e3, 3),
             "gcups": round(cells / dt / 1e9, 2),
-            "what": f"traceback of each query's top-{args.k} hits"}
+            "ms_per_query_first_pass": round(dts[0] / len(queries) * 1e3, 3),
+            "what": f"traceback of each query's top-{args.k} hits, second pass (the first grows the workspaces)"}
 
 
 def run_batched(args, swmi, sd, torch):
