@@ -353,12 +353,12 @@ struct FrameStrip {
 #pragma unroll
         for (int j4 = 0; j4 < T / 4; ++j4) Pn[j4] = nxt[j4];
         // The cells of FrameStrip::cell, in an order that puts independent
-        // work between each column's dependent steps h -> t -> f: gfx950 holds
-        // a packed instruction back one cycle when it reads the result of the
-        // packed instruction just before it.  Between h and t goes the next
-        // column's diagonal sum (H[j] still holds row r - 1 there); between t
-        // and f the running best of an even column, and the E update of the
-        // column before (E[j] is next read by the row below).
+        // work between each column's dependent steps h -> t -> f: gfx950 needs
+        // a wait state before a packed fp16 instruction that reads the result
+        // of the packed fp16 instruction just before it.  Between h and t goes
+        // the next column's diagonal sum (H[j] still holds row r - 1 there);
+        // between t and f the running best of an even column, and the E
+        // update of the column before (E[j] is next read by the row below).
         V d = as_v<V>(hb_prev) + as_v<V>(Pc[0].x);
         V tp = d;
 #pragma unroll

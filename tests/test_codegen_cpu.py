@@ -1,8 +1,8 @@
 """Code generation of the fp16 kernels' hot loops (CPU: hipcc cross-compiles).
 
-gfx950 needs one wait state between a packed 16-bit instruction and a packed
-instruction right after it that reads its result; the compiler emits it as
-``s_nop``.  The fp16 kernels write their cell steps so that independent work
+gfx950 needs one wait state between a packed fp16 instruction and a packed
+fp16 instruction right after it that reads its result; the compiler emits it
+as ``s_nop``.  The fp16 kernels write their cell steps so that independent work
 sits between the dependent ones.  This test compiles the kernel source with
 the library's own flags and checks, in the largest basic block of each hot
 kernel (its step loop), that the wait states stay well below what the
